@@ -1,0 +1,315 @@
+/*
+ * sd_oracle.c -- plain FP64 CPU oracle for the all-pairs mobility product of
+ * leading-order Stokesian dynamics (Kopp & Hoefling, "GPU-accelerated
+ * simulation of colloidal suspensions with direct hydrodynamic interactions",
+ * Eur. Phys. J. Special Topics 2012).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the slow, obviously correct
+ * definition that the GPU library is checked against.  Only the test suite,
+ * the smoke check and the CPU-baseline leg of the benchmark may load it; the
+ * product path never does.  It shares no code, header or constant with the
+ * HIP library.
+ *
+ * Everything is double precision.  Loops are the plain definitions: no
+ * blocking, no symmetry exploitation, no reordering.  The outer loop over
+ * particles may run on several threads (OpenMP); each output element is still
+ * produced by one thread in a fixed order, so results are deterministic.
+ *
+ * Readings where the paper is silent (documented next to the code that uses
+ * them):
+ *   - overlap form of the pair tensor for r < 2a (not in the paper; the
+ *     Rotne-Prager-Yamakawa regularisation), continuous at r = 2a;
+ *   - coincident distinct particles (r = 0): mu0*I with the overlap form,
+ *     zero contribution otherwise;
+ *   - AB2 integrator (the paper only suggests higher-order schemes), first
+ *     step explicit Euler;
+ *   - the velocity at step n is computed from the positions at step n before
+ *     the positions move (standard explicit Euler).
+ */
+#include <math.h>
+#include <stddef.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+typedef struct {
+    double a;      /* sphere radius */
+    double eta;    /* shear viscosity */
+    int tensor;    /* 0 = Rotne-Prager (Eq. 7b), 1 = Oseen (Eq. 4) */
+    int overlap;   /* 0 = far form at every r > 0, 1 = overlap form for r < 2a */
+} oracle_params;
+
+enum { OR_RPY = 0, OR_OSEEN = 1 };
+
+/* Stokes mobility of a single sphere, mu0 = 1/(6 pi eta a): Eq. (7a), Sec. 2.2. */
+static double stokes_mobility(const oracle_params* p)
+{
+    return 1.0 / (6.0 * M_PI * p->eta * p->a);
+}
+
+/*
+ * 3x3 pair block T(r) of the mobility matrix for r = r_i - r_j, i != j,
+ * row-major into T[9].
+ *
+ *  Oseen, Eq. (4), Sec. 2.2:   G(r) = (I + rhat rhat) / (8 pi eta r)
+ *  Rotne-Prager, Eq. (7b):     T(r) = mu0 (3a/4r)(I + rhat rhat)
+ *                                   + mu0 (a^3/2r^3)(I - 3 rhat rhat)
+ *  Overlap (r < 2a, reading; not in the paper):
+ *                              T(r) = mu0 [(1 - 9r/32a) I + (3r/32a) rhat rhat]
+ *  Coincident distinct particles (r = 0, reading): mu0 I with the overlap form,
+ *  zero otherwise (the far forms are singular there).
+ */
+void oracle_pair_tensor(const oracle_params* p, const double r[3], double T[9])
+{
+    const double mu0 = stokes_mobility(p);
+    const double a = p->a;
+    const double rr = sqrt(r[0] * r[0] + r[1] * r[1] + r[2] * r[2]);
+    double cI, cP;  /* T = cI * I + cP * rhat rhat */
+
+    if (rr == 0.0) {
+        for (int k = 0; k < 9; ++k) T[k] = 0.0;
+        if (p->overlap && p->tensor == OR_RPY) T[0] = T[4] = T[8] = mu0;
+        return;
+    }
+    if (p->tensor == OR_OSEEN) {
+        const double g = 1.0 / (8.0 * M_PI * p->eta * rr);
+        cI = g;
+        cP = g;
+    } else if (p->overlap && rr < 2.0 * a) {
+        cI = mu0 * (1.0 - 9.0 * rr / (32.0 * a));
+        cP = mu0 * (3.0 * rr / (32.0 * a));
+    } else {
+        const double t1 = mu0 * 3.0 * a / (4.0 * rr);            /* (I + rr) part */
+        const double t3 = mu0 * a * a * a / (2.0 * rr * rr * rr); /* (I - 3rr) part */
+        cI = t1 + t3;
+        cP = t1 - 3.0 * t3;
+    }
+    double h[3] = { r[0] / rr, r[1] / rr, r[2] / rr };
+    for (int al = 0; al < 3; ++al)
+        for (int be = 0; be < 3; ++be)
+            T[3 * al + be] = (al == be ? cI : 0.0) + cP * h[al] * h[be];
+}
+
+/* velocity of one particle i: v_i = mu0 F_i + sum_{j != i} T(r_i - r_j) F_j, Eq. (7a) */
+static void velocity_of(const oracle_params* p, int64_t n, const double* x, const double* f,
+                        int64_t i, double out[3])
+{
+    const double mu0 = stokes_mobility(p);
+    double v[3] = { mu0 * f[3 * i + 0], mu0 * f[3 * i + 1], mu0 * f[3 * i + 2] };
+    for (int64_t j = 0; j < n; ++j) {
+        if (j == i) continue;
+        double r[3] = { x[3 * i + 0] - x[3 * j + 0], x[3 * i + 1] - x[3 * j + 1],
+                        x[3 * i + 2] - x[3 * j + 2] };
+        double T[9];
+        oracle_pair_tensor(p, r, T);
+        for (int al = 0; al < 3; ++al)
+            v[al] += T[3 * al + 0] * f[3 * j + 0] + T[3 * al + 1] * f[3 * j + 1]
+                   + T[3 * al + 2] * f[3 * j + 2];
+    }
+    out[0] = v[0]; out[1] = v[1]; out[2] = v[2];
+}
+
+/* All-pairs mobility product, Eq. (7a), step 3 of the algorithm of Sec. 3.1.
+ * x, f, v: n x 3 row-major (AoS). */
+void oracle_mobility(const oracle_params* p, int64_t n, const double* x, const double* f, double* v)
+{
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t i = 0; i < n; ++i) velocity_of(p, n, x, f, i, v + 3 * i);
+}
+
+/* The same product for a subset of rows (used for sampled checks at large n). */
+void oracle_mobility_rows(const oracle_params* p, int64_t n, const double* x, const double* f,
+                          int64_t nrows, const int64_t* rows, double* v_rows)
+{
+#pragma omp parallel for schedule(dynamic, 4)
+    for (int64_t q = 0; q < nrows; ++q) velocity_of(p, n, x, f, rows[q], v_rows + 3 * q);
+}
+
+/* Dense 3n x 3n mobility matrix with blocks mu_ij (Eq. 7a): mu_ii = mu0 I,
+ * mu_ij = T(r_i - r_j).  Row-major, M[(3i+al)*(3n) + 3j+be].  Tiny n only. */
+void oracle_dense_mobility(const oracle_params* p, int64_t n, const double* x, double* M)
+{
+    const double mu0 = stokes_mobility(p);
+    const int64_t ld = 3 * n;
+    for (int64_t i = 0; i < n; ++i)
+        for (int64_t j = 0; j < n; ++j) {
+            double T[9];
+            if (i == j) {
+                for (int k = 0; k < 9; ++k) T[k] = 0.0;
+                T[0] = T[4] = T[8] = mu0;
+            } else {
+                double r[3] = { x[3 * i] - x[3 * j], x[3 * i + 1] - x[3 * j + 1],
+                                x[3 * i + 2] - x[3 * j + 2] };
+                oracle_pair_tensor(p, r, T);
+            }
+            for (int al = 0; al < 3; ++al)
+                for (int be = 0; be < 3; ++be) M[(3 * i + al) * ld + 3 * j + be] = T[3 * al + be];
+        }
+}
+
+/*
+ * Time integration of dx/dt = M(x) F with constant forces (Sec. 3.1, step 1
+ * "update particle positions" with the velocities of step 3).
+ *   integrator 0: explicit Euler,  x_{k+1} = x_k + dt v_k            (Sec. 3.1)
+ *   integrator 1: Adams-Bashforth 2, x_{k+1} = x_k + dt (3/2 v_k - 1/2 v_{k-1})
+ *                 (reading: not in the paper; the step with global index 0 is
+ *                 an Euler step)
+ * v_k = M(x_k) F.  step0 is the global index of the first step taken, so a run
+ * can be resumed; v_prev holds v_{k-1} on entry (ignored when step0 == 0) and
+ * v_{last} on exit.  If traj != NULL, x is copied to traj every `stride` steps,
+ * starting with the initial state: traj holds floor(steps/stride)+1 frames.
+ */
+int oracle_run(const oracle_params* p, int64_t n, double* x, const double* f, double dt,
+               int64_t steps, int64_t step0, int integrator, double* v_prev, double* traj,
+               int64_t stride)
+{
+    double* v = (double*)malloc(sizeof(double) * 3 * (size_t)n);
+    if (!v) return 1;
+    int64_t frame = 0;
+    if (traj) memcpy(traj + 3 * n * frame++, x, sizeof(double) * 3 * (size_t)n);
+    for (int64_t s = 0; s < steps; ++s) {
+        oracle_mobility(p, n, x, f, v);
+        const int euler = (integrator == 0) || (step0 + s == 0);
+        for (int64_t k = 0; k < 3 * n; ++k) {
+            if (euler) x[k] = x[k] + dt * v[k];
+            else x[k] = x[k] + dt * (1.5 * v[k] - 0.5 * v_prev[k]);
+        }
+        if (v_prev) memcpy(v_prev, v, sizeof(double) * 3 * (size_t)n);
+        if (traj && stride > 0 && (s + 1) % stride == 0)
+            memcpy(traj + 3 * n * frame++, x, sizeof(double) * 3 * (size_t)n);
+    }
+    free(v);
+    return 0;
+}
+
+/*
+ * Gradient with respect to r of the bilinear form u . T(r) w, for r != 0.
+ * With T = cI(r) I + cP(r) rhat rhat written as  A(r) I + Bt(r) r r  (Bt = cP/r^2):
+ *   grad_r [u.T.w] = A'(r) (u.w) rhat + Bt'(r) (u.r)(w.r) rhat + Bt(r) [(w.r) u + (u.r) w]
+ * Derivatives of the three forms of oracle_pair_tensor:
+ *   Rotne-Prager far:  A = mu0(3a/4r + a^3/2r^3),  Bt = mu0(3a/4r^3 - 3a^3/2r^5)
+ *   Oseen:             A = 1/(8 pi eta r),         Bt = 1/(8 pi eta r^3)
+ *   overlap (r < 2a):  A = mu0(1 - 9r/32a),        Bt = mu0 3/(32 a r)
+ * At r = 0 the gradient is defined as zero (measure-zero set).  At r = 2a the
+ * far form is used (one-sided derivative), matching oracle_pair_tensor.
+ */
+void oracle_pair_grad(const oracle_params* p, const double r[3], const double u[3],
+                      const double w[3], double g[3])
+{
+    const double mu0 = stokes_mobility(p);
+    const double a = p->a;
+    const double rr = sqrt(r[0] * r[0] + r[1] * r[1] + r[2] * r[2]);
+    g[0] = g[1] = g[2] = 0.0;
+    if (rr == 0.0) return;
+    double Bt, dA, dBt;
+    if (p->tensor == OR_OSEEN) {
+        const double c = 1.0 / (8.0 * M_PI * p->eta);
+        Bt = c / (rr * rr * rr);
+        dA = -c / (rr * rr);
+        dBt = -3.0 * c / (rr * rr * rr * rr);
+    } else if (p->overlap && rr < 2.0 * a) {
+        Bt = mu0 * 3.0 / (32.0 * a * rr);
+        dA = -mu0 * 9.0 / (32.0 * a);
+        dBt = -mu0 * 3.0 / (32.0 * a * rr * rr);
+    } else {
+        const double r2 = rr * rr, r3 = r2 * rr, r4 = r2 * r2, r5 = r4 * rr, r6 = r3 * r3;
+        const double a3 = a * a * a;
+        Bt = mu0 * (3.0 * a / (4.0 * r3) - 3.0 * a3 / (2.0 * r5));
+        dA = mu0 * (-3.0 * a / (4.0 * r2) - 3.0 * a3 / (2.0 * r4));
+        dBt = mu0 * (-9.0 * a / (4.0 * r4) + 15.0 * a3 / (2.0 * r6));
+    }
+    const double uw = u[0] * w[0] + u[1] * w[1] + u[2] * w[2];
+    const double ur = u[0] * r[0] + u[1] * r[1] + u[2] * r[2];
+    const double wr = w[0] * r[0] + w[1] * r[1] + w[2] * r[2];
+    for (int k = 0; k < 3; ++k)
+        g[k] = (dA * uw + dBt * ur * wr) * r[k] / rr + Bt * (wr * u[k] + ur * w[k]);
+}
+
+/* Transposed mobility product (M^T y)_i = mu0 y_i + sum_{j != i} T(r_j - r_i)^T y_j.
+ * Written from the definition of the transpose; that it equals M y is a
+ * property the tests check, not an assumption made here. */
+void oracle_mobility_transpose(const oracle_params* p, int64_t n, const double* x, const double* y,
+                               double* out)
+{
+    const double mu0 = stokes_mobility(p);
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t i = 0; i < n; ++i) {
+        double acc[3] = { mu0 * y[3 * i], mu0 * y[3 * i + 1], mu0 * y[3 * i + 2] };
+        for (int64_t j = 0; j < n; ++j) {
+            if (j == i) continue;
+            double r[3] = { x[3 * j] - x[3 * i], x[3 * j + 1] - x[3 * i + 1],
+                            x[3 * j + 2] - x[3 * i + 2] };
+            double T[9];
+            oracle_pair_tensor(p, r, T);
+            for (int be = 0; be < 3; ++be)  /* column be of block mu_ji = row be of its transpose */
+                acc[be] += T[0 * 3 + be] * y[3 * j] + T[1 * 3 + be] * y[3 * j + 1]
+                         + T[2 * 3 + be] * y[3 * j + 2];
+        }
+        out[3 * i] = acc[0]; out[3 * i + 1] = acc[1]; out[3 * i + 2] = acc[2];
+    }
+}
+
+/*
+ * Position gradient of the scalar  s(x) = sum_k lam_k . v_k(x),  v = M(x) F:
+ *   d s / d x_i = sum_{j != i} d/dx_i [ lam_i . T(x_i - x_j) F_j ]
+ *               + sum_{j != i} d/dx_i [ lam_j . T(x_j - x_i) F_i ]
+ * (x_i enters v_i through every T(x_i - x_j) and v_j through T(x_j - x_i)).
+ * The chain rule gives +grad_r at r = x_i - x_j for the first term and
+ * -grad_r at r = x_j - x_i for the second.
+ */
+void oracle_mobility_vjp_x(const oracle_params* p, int64_t n, const double* x, const double* f,
+                           const double* lam, double* gx)
+{
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t i = 0; i < n; ++i) {
+        double acc[3] = { 0.0, 0.0, 0.0 };
+        for (int64_t j = 0; j < n; ++j) {
+            if (j == i) continue;
+            double rij[3] = { x[3 * i] - x[3 * j], x[3 * i + 1] - x[3 * j + 1],
+                              x[3 * i + 2] - x[3 * j + 2] };
+            double rji[3] = { -rij[0], -rij[1], -rij[2] };
+            double g1[3], g2[3];
+            oracle_pair_grad(p, rij, lam + 3 * i, f + 3 * j, g1);
+            oracle_pair_grad(p, rji, lam + 3 * j, f + 3 * i, g2);
+            for (int k = 0; k < 3; ++k) acc[k] += g1[k] - g2[k];
+        }
+        gx[3 * i] = acc[0]; gx[3 * i + 1] = acc[1]; gx[3 * i + 2] = acc[2];
+    }
+}
+
+/*
+ * Discrete adjoint of `steps` explicit-Euler steps x_{k+1} = x_k + dt M(x_k) F
+ * for a loss L(x_steps) whose gradient lam_N = dL/dx_steps is given.
+ *   lam_k = lam_{k+1} + dt * d/dx [lam_{k+1} . M(x_k) F]
+ *   dL/dF += dt * M(x_k)^T lam_{k+1}
+ *   dL/dx_0 = lam_0
+ * The forward trajectory is recomputed and kept whole (plain, not checkpointed).
+ */
+int oracle_run_adjoint_euler(const oracle_params* p, int64_t n, const double* x0, const double* f,
+                             double dt, int64_t steps, const double* lam_final, double* grad_x0,
+                             double* grad_f)
+{
+    const size_t m = 3 * (size_t)n;
+    double* xs = (double*)malloc(sizeof(double) * m * (size_t)(steps + 1));
+    double* lam = (double*)malloc(sizeof(double) * m);
+    double* tmp = (double*)malloc(sizeof(double) * m);
+    double* v = (double*)malloc(sizeof(double) * m);
+    if (!xs || !lam || !tmp || !v) { free(xs); free(lam); free(tmp); free(v); return 1; }
+    memcpy(xs, x0, sizeof(double) * m);
+    for (int64_t s = 0; s < steps; ++s) {
+        oracle_mobility(p, n, xs + m * s, f, v);
+        for (size_t k = 0; k < m; ++k) xs[m * (s + 1) + k] = xs[m * s + k] + dt * v[k];
+    }
+    memcpy(lam, lam_final, sizeof(double) * m);
+    for (size_t k = 0; k < m; ++k) grad_f[k] = 0.0;
+    for (int64_t s = steps - 1; s >= 0; --s) {
+        const double* xk = xs + m * s;
+        oracle_mobility_transpose(p, n, xk, lam, tmp);
+        for (size_t k = 0; k < m; ++k) grad_f[k] += dt * tmp[k];
+        oracle_mobility_vjp_x(p, n, xk, f, lam, tmp);
+        for (size_t k = 0; k < m; ++k) lam[k] += dt * tmp[k];
+    }
+    memcpy(grad_x0, lam, sizeof(double) * m);
+    free(xs); free(lam); free(tmp); free(v);
+    return 0;
+}

@@ -1,0 +1,446 @@
+"""Pins of the FP64 oracle against what the paper and the mathematics fix.
+
+None of these re-types the oracle's own pair-tensor formula: each value comes
+from an independent route (Faxen surface averages, the Laplacian identity of
+Eq. 7b, closed forms at contact, eigenvalues, divergence, finite differences,
+convergence orders, the four-sphere cluster of Sec. 4).
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from paper_1205_6333_amd import workloads as W
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _rot(seed):
+    q, r = np.linalg.qr(np.random.default_rng(seed).standard_normal((3, 3)))
+    q = q * np.sign(np.diag(r))
+    if np.linalg.det(q) < 0:
+        q[:, 0] = -q[:, 0]
+    return q
+
+
+# ---------------------------------------------------------------- closed forms
+
+def test_single_sphere_is_stokes_drag(orc):
+    """n = 1: v = F / (6 pi eta a) (Stokes mobility, Eq. 7a)."""
+    for a, eta in [(1.0, 1 / (6 * np.pi)), (0.37, 2.5), (4.0, 0.01)]:
+        p = orc.params(a=a, eta=eta)
+        F = np.array([[0.3, -1.2, 2.0]])
+        v = orc.mobility(p, np.array([[1.0, 2.0, 3.0]]), F)
+        np.testing.assert_allclose(v, F / (6 * np.pi * eta * a), rtol=1e-15)
+
+
+def test_two_spheres_at_contact(orc):
+    """Two equal forces at r = 2a: (1 + 3/8 + 1/16) mu0 F perpendicular to the
+    line of centres, (1 + 3/4 - 1/8) mu0 F along it (Eq. 7 at contact)."""
+    a, eta = 1.3, 0.7
+    mu0 = 1 / (6 * np.pi * eta * a)
+    p = orc.params(a=a, eta=eta)
+    x = np.array([[0.0, 0.0, 0.0], [2 * a, 0.0, 0.0]])
+    v = orc.mobility(p, x, np.array([[0, 0, 1.0], [0, 0, 1.0]]))
+    np.testing.assert_allclose(v[:, 2], 23 / 16 * mu0, rtol=1e-14)
+    np.testing.assert_allclose(v[:, :2], 0, atol=1e-16)
+    v = orc.mobility(p, x, np.array([[1.0, 0, 0], [1.0, 0, 0]]))
+    np.testing.assert_allclose(v[:, 0], 13 / 8 * mu0, rtol=1e-14)
+
+
+def test_two_sphere_eigenvalues(orc):
+    """6x6 mobility of two spheres: eigenvalues mu0(1 +- (3a/2r - a^3/r^3)) and
+    mu0(1 +- (3a/4r + a^3/2r^3)) (twice), all positive for r >= 2a."""
+    a = 1.0
+    p = orc.params(a=a)
+    for r in [2.0, 2.2, 3.7, 10.0]:
+        x = np.array([[0, 0, 0], [r / np.sqrt(3)] * 3])
+        ev = np.sort(np.linalg.eigvalsh(orc.dense_mobility(p, x)))
+        par = 3 * a / (2 * r) - a ** 3 / r ** 3
+        per = 3 * a / (4 * r) + a ** 3 / (2 * r ** 3)
+        ref = np.sort([1 + par, 1 - par, 1 + per, 1 + per, 1 - per, 1 - per])
+        np.testing.assert_allclose(ev, ref, rtol=1e-13)
+        assert ev.min() > 0
+
+
+# ------------------------------------------------ first-principles derivations
+
+def _oseen(y, eta):
+    """Eq. 4, vectorised over y (..., 3)."""
+    r = np.linalg.norm(y, axis=-1)
+    h = y / r[..., None]
+    return (np.eye(3) + h[..., :, None] * h[..., None, :]) / (8 * np.pi * eta * r[..., None, None])
+
+
+def _sphere_nodes(a, n_theta, n_phi):
+    from numpy.polynomial.legendre import leggauss
+    c, w = leggauss(n_theta)
+    ph = (np.arange(n_phi) + 0.5) * 2 * np.pi / n_phi
+    s = np.sqrt(1 - c * c)
+    pts = np.stack([s[:, None] * np.cos(ph), s[:, None] * np.sin(ph),
+                    np.repeat(c[:, None], n_phi, 1)], -1).reshape(-1, 3) * a
+    wts = np.repeat(w[:, None] / 2 / n_phi, n_phi, 1).reshape(-1)
+    return pts, wts
+
+
+@pytest.mark.parametrize("r", [3.0, 4.5, 9.0])
+def test_far_form_is_double_surface_average_of_oseen(orc, r):
+    """Eq. 5-6: the pair tensor for separated spheres is the Oseen tensor (Eq. 4)
+    averaged over both sphere surfaces.  Computed here by brute-force
+    quadrature of Eq. 4 and compared with the oracle's Eq. 7b."""
+    a, eta = 1.0, 0.45
+    pts, wts = _sphere_nodes(a, 40, 40)
+    axis = np.array([0.3, -0.5, 0.8])
+    axis /= np.linalg.norm(axis)
+    R = r * axis
+    T = np.zeros((3, 3))
+    for p1, w1 in zip(pts, wts):
+        T += w1 * np.einsum("k,kab->ab", wts, _oseen(R + p1 - pts, eta))
+    Tor = orc.pair_tensor(orc.params(a=a, eta=eta), R)
+    np.testing.assert_allclose(Tor, T, rtol=0, atol=1e-10 * np.abs(T).max())
+
+
+@pytest.mark.parametrize("r", [0.0, 0.25, 0.7, 1.0, 1.5, 1.99, 2.0, 2.6])
+def test_overlap_form_is_surface_average_of_single_layer(orc, r):
+    """The overlap reading for r < 2a (not printed in the paper) is the same
+    Faxen average as for r >= 2a: the flow of a sphere carrying a uniform
+    surface force density is uniform (= mu0 F, Stokes' law) inside the sphere
+    and (1 + a^2/6 Laplacian) G F outside (Eq. 5); its average over the second
+    sphere's surface is computed here by quadrature split at the kink where
+    the second surface crosses the first."""
+    from numpy.polynomial.legendre import leggauss
+    a, eta = 1.0, 1 / (6 * np.pi)
+    mu0 = 1 / (6 * np.pi * eta * a)
+
+    def single_layer(y):
+        ry = np.linalg.norm(y, axis=-1)
+        out = np.empty(y.shape[:-1] + (3, 3))
+        inside = ry < a
+        out[inside] = mu0 * np.eye(3)
+        yo = y[~inside]
+        ro = ry[~inside][:, None, None]
+        h = yo / ry[~inside][:, None]
+        P = h[:, :, None] * h[:, None, :]
+        out[~inside] = ((np.eye(3) + P) + a * a / (3 * ro ** 2) * (np.eye(3) - 3 * P)) \
+            / (8 * np.pi * eta * ro)
+        return out
+
+    ck = -r / (2 * a)
+    segs = [(-1.0, ck), (ck, 1.0)] if -1 < ck < 1 else [(-1.0, 1.0)]
+    x, w = leggauss(200)
+    nph = 64
+    ph = (np.arange(nph) + 0.5) * 2 * np.pi / nph
+    T = np.zeros((3, 3))
+    for lo, hi in segs:
+        c = 0.5 * (hi - lo) * x + 0.5 * (hi + lo)
+        wc = 0.5 * (hi - lo) * w
+        s = np.sqrt(1 - c * c)
+        n = np.stack([s[:, None] * np.cos(ph), s[:, None] * np.sin(ph),
+                      np.repeat(c[:, None], nph, 1)], -1)
+        val = single_layer((np.array([0, 0, r]) + a * n).reshape(-1, 3)).reshape(len(c), nph, 3, 3)
+        T += (val * wc[:, None, None, None]).sum((0, 1)) / nph / 2
+    p = orc.params(a=a, eta=eta, overlap=True)
+    Tor = orc.pair_tensor(p, [0.0, 0.0, r])
+    np.testing.assert_allclose(Tor, T, rtol=0, atol=1e-11)
+
+
+@pytest.mark.parametrize("r", [2.3, 3.0, 7.5])
+def test_rotne_prager_is_laplacian_correction_of_oseen(orc, r):
+    """Eq. 7b, first equality: T = (1 + a^2/3 Laplacian) G.  The Laplacian of
+    the oracle's Oseen tensor is taken by central differences; this ties the
+    Oseen mode's prefactor to the (independently pinned) Rotne-Prager mode."""
+    a, eta = 1.1, 0.8
+    po = orc.params(a=a, eta=eta, tensor=orc.OSEEN)
+    pr = orc.params(a=a, eta=eta)
+    R = r * np.array([0.48, 0.6, -0.64])
+    h = 2e-3
+    lap = -6 * orc.pair_tensor(po, R)
+    for k in range(3):
+        e = np.zeros(3)
+        e[k] = h
+        lap += orc.pair_tensor(po, R + e) + orc.pair_tensor(po, R - e)
+    lap /= h * h
+    T = orc.pair_tensor(po, R) + a * a / 3 * lap
+    np.testing.assert_allclose(orc.pair_tensor(pr, R), T, rtol=0,
+                               atol=3e-7 * np.abs(T).max())
+
+
+@pytest.mark.parametrize("tensor,overlap,r", [(0, False, 3.1), (0, True, 1.3), (0, True, 0.4),
+                                              (1, False, 2.5), (0, False, 1.3)])
+def test_flow_is_divergence_free(orc, tensor, overlap, r):
+    """Incompressibility (Eq. 3): the velocity a force induces at a probe,
+    u(r) = T(r) F, has zero divergence in r, in every regime of the tensor."""
+    p = orc.params(a=1.0, eta=0.3, tensor=tensor, overlap=overlap)
+    F = np.array([0.2, -0.7, 1.1])
+    R = r * np.array([0.36, 0.48, 0.8])
+    h = 1e-4 * r
+
+    def u(pt):
+        x = np.array([pt, [0.0, 0.0, 0.0]])
+        return orc.mobility(p, x, np.array([[0.0, 0.0, 0.0], F]))[0]
+
+    div = 0.0
+    for k in range(3):
+        e = np.zeros(3)
+        e[k] = h
+        div += (u(R + e)[k] - u(R - e)[k]) / (2 * h)
+    # a wrong coefficient gives |div| ~ |u|/r; FD truncation is ~ (h/r)^2 |u|/r
+    assert abs(div) < 1e-6 * np.linalg.norm(u(R)) / r
+
+
+def test_overlap_continuity_and_coincidence(orc):
+    """Overlap form: continuous at r = 2a (7/16 I + 3/16 rhat rhat in mu0 units),
+    tends to mu0 I at r -> 0; without it, coincident particles contribute 0."""
+    a, eta = 2.0, 0.05
+    mu0 = 1 / (6 * np.pi * eta * a)
+    po = orc.params(a=a, eta=eta, overlap=True)
+    e = np.array([0.0, 0.6, 0.8])
+    P = np.outer(e, e)
+    lo = orc.pair_tensor(po, (2 * a) * (1 - 1e-12) * e)
+    hi = orc.pair_tensor(po, (2 * a) * e)
+    np.testing.assert_allclose(lo, hi, atol=1e-10 * mu0)
+    np.testing.assert_allclose(hi, mu0 * (7 / 16 * np.eye(3) + 3 / 16 * P), atol=1e-14 * mu0)
+    np.testing.assert_allclose(orc.pair_tensor(po, 1e-12 * e), mu0 * np.eye(3), atol=1e-12 * mu0)
+    np.testing.assert_allclose(orc.pair_tensor(po, [0, 0, 0]), mu0 * np.eye(3))
+    np.testing.assert_array_equal(orc.pair_tensor(orc.params(a=a, eta=eta), [0, 0, 0]), 0)
+    np.testing.assert_array_equal(
+        orc.pair_tensor(orc.params(a=a, eta=eta, tensor=orc.OSEEN), [0, 0, 0]), 0)
+
+
+def test_oseen_is_far_field_of_rotne_prager(orc):
+    """G is the r >> a limit of T: the difference is (a^2/r^2) relative."""
+    po = orc.params(tensor=orc.OSEEN)
+    pr = orc.params()
+    for r in [50.0, 500.0, 5000.0]:
+        R = r * np.array([0.0, 0.6, 0.8])
+        To, Tr = orc.pair_tensor(po, R), orc.pair_tensor(pr, R)
+        rel = np.abs(To - Tr).max() / np.abs(To).max()
+        assert 0.2 / r ** 2 < rel < 1.0 / r ** 2
+
+
+# ------------------------------------------------------- matrix properties
+
+def test_dense_mobility_symmetric_positive_definite(orc):
+    """M = M^T (block symmetry mu_ij = mu_ji^T, Sec. 3.2/3.3) and M > 0 for all
+    r_ij >= 2a (Rotne & Prager, Sec. 2.2); the overlap form keeps M > 0 for
+    overlapping configurations."""
+    x = W.random_suspension(48, phi=0.2, min_dist=2.0, seed=11)
+    M = orc.dense_mobility(orc.params(), x)
+    np.testing.assert_allclose(M, M.T, rtol=0, atol=1e-15)
+    assert np.linalg.eigvalsh(M).min() > 0
+    x = np.random.default_rng(12).normal(0, 1.2, size=(40, 3))  # heavily overlapping
+    M = orc.dense_mobility(orc.params(overlap=True), x)
+    np.testing.assert_allclose(M, M.T, rtol=0, atol=1e-15)
+    assert np.linalg.eigvalsh(M).min() > 0
+
+
+def test_product_matches_dense_matrix_and_transpose(orc):
+    x = W.random_suspension(30, phi=0.1, seed=5)
+    f = W.gaussian_forces(30, seed=6)
+    g = W.gaussian_forces(30, seed=7)
+    for p in [orc.params(), orc.params(tensor=orc.OSEEN), orc.params(overlap=True, a=1.6)]:
+        M = orc.dense_mobility(p, x)
+        np.testing.assert_allclose(orc.mobility(p, x, f).reshape(-1), M @ f.reshape(-1),
+                                   rtol=1e-13, atol=1e-15)
+        np.testing.assert_allclose(orc.mobility_transpose(p, x, g).reshape(-1),
+                                   M.T @ g.reshape(-1), rtol=1e-13, atol=1e-15)
+        # dot-product test <M g, F> = <g, M F>
+        lhs = np.dot(orc.mobility(p, x, g).reshape(-1), f.reshape(-1))
+        rhs = np.dot(g.reshape(-1), orc.mobility(p, x, f).reshape(-1))
+        assert abs(lhs - rhs) < 1e-13 * abs(lhs)
+
+
+def test_invariants(orc):
+    """Linearity in F, translation invariance, rotation and permutation
+    equivariance of the product."""
+    x = W.random_suspension(64, phi=0.05, seed=21)
+    f = W.gaussian_forces(64, seed=22)
+    g = W.gaussian_forces(64, seed=23)
+    for p in [orc.params(), orc.params(tensor=orc.OSEEN), orc.params(overlap=True, a=2.0)]:
+        v = orc.mobility(p, x, f)
+        np.testing.assert_allclose(orc.mobility(p, x, 2.5 * f - g),
+                                   2.5 * v - orc.mobility(p, x, g), rtol=1e-12, atol=1e-13)
+        np.testing.assert_allclose(orc.mobility(p, x + np.array([3.0, -7.0, 11.0]), f), v,
+                                   rtol=1e-11, atol=1e-12)
+        Q = _rot(24)
+        np.testing.assert_allclose(orc.mobility(p, x @ Q.T, f @ Q.T), v @ Q.T, rtol=1e-12,
+                                   atol=1e-13)
+        perm = np.random.default_rng(25).permutation(64)
+        np.testing.assert_allclose(orc.mobility(p, x[perm], f[perm]), v[perm], rtol=1e-13,
+                                   atol=1e-14)
+
+
+def test_sampled_rows_match_full_product(orc):
+    x = W.random_suspension(200, seed=31)
+    f = W.gaussian_forces(200, seed=32)
+    p = orc.params()
+    rows = np.array([0, 7, 199, 100])
+    np.testing.assert_array_equal(orc.mobility_rows(p, x, f, rows), orc.mobility(p, x, f)[rows])
+
+
+# ------------------------------------------------------------ time loop
+
+def test_single_sphere_trajectory_is_exact(orc):
+    """n = 1 moves at the Stokes velocity: x(t) = x0 + mu0 F t (both schemes)."""
+    p = orc.params(a=0.5, eta=0.25)
+    mu0 = 1 / (6 * np.pi * 0.25 * 0.5)
+    x0 = np.array([[1.0, 2.0, 3.0]])
+    F = np.array([[0.0, 0.5, -2.0]])
+    for integ in (orc.EULER, orc.AB2):
+        x, _, _ = orc.run(p, x0, F, 0.125, 64, integ)
+        np.testing.assert_allclose(x, x0 + mu0 * F * 8.0, rtol=1e-14)
+
+
+def test_integrator_orders(orc):
+    """Euler is first order in dt, AB2 (reading) second order: halving dt halves
+    (quarters) the error against a fine AB2 reference."""
+    p = orc.params()
+    x0, F = W.square_xz()
+    T = 20.0
+    ref, _, _ = orc.run(p, x0, F, T / 16000, 16000, orc.AB2)
+    for integ, order in ((orc.EULER, 1), (orc.AB2, 2)):
+        errs = []
+        for nsteps in (100, 200, 400):
+            x, _, _ = orc.run(p, x0, F, T / nsteps, nsteps, integ)
+            errs.append(np.abs(x - ref).max())
+        ratios = [errs[0] / errs[1], errs[1] / errs[2]]
+        for q in ratios:
+            assert abs(np.log2(q) - order) < 0.15, (integ, errs)
+
+
+def test_run_resumes_bitwise(orc):
+    p = orc.params(overlap=True)
+    x0 = W.random_suspension(20, phi=0.2, min_dist=2.0, seed=41)
+    F = W.gravity_forces(20)
+    for integ in (orc.EULER, orc.AB2):
+        full, vfull, _ = orc.run(p, x0, F, 0.05, 30, integ)
+        half, vh, _ = orc.run(p, x0, F, 0.05, 13, integ)
+        rest, vr, _ = orc.run(p, half, F, 0.05, 17, integ, step0=13, v_prev=vh)
+        np.testing.assert_array_equal(rest, full)
+        np.testing.assert_array_equal(vr, vfull)
+
+
+def test_square_cluster_symmetries(orc):
+    """Four spheres on a square in the x-z plane (the 4-particle workload):
+    y stays exactly 0 and the motion is mirror symmetric under x -> -x
+    (1 <-> 2, 3 <-> 4)."""
+    p = orc.params()
+    x0, F = W.square_xz()
+    x, _, traj = orc.run(p, x0, F, 0.01, 10000, orc.EULER, stride=100)
+    assert np.all(traj[:, :, 1] == 0.0)
+    np.testing.assert_allclose(traj[:, 0, 0], -traj[:, 1, 0], rtol=0, atol=1e-11)
+    np.testing.assert_allclose(traj[:, 3, 0], -traj[:, 2, 0], rtol=0, atol=1e-11)
+    np.testing.assert_allclose(traj[:, 0, 2], traj[:, 1, 2], rtol=0, atol=1e-11)
+    # the cluster sediments: centre of mass moves down faster than a single sphere
+    assert x[:, 2].mean() < -100.0
+
+
+def _maxima(t, y):
+    """Times of local maxima refined by parabolic fits (as in Sec. 4)."""
+    out = []
+    for k in range(1, len(y) - 1):
+        if y[k] > y[k - 1] and y[k] >= y[k + 1]:
+            c = np.polyfit(t[k - 1:k + 2] - t[k], y[k - 1:k + 2], 2)
+            out.append(t[k] - c[1] / (2 * c[0]))
+    return np.array(out)
+
+
+def test_four_sphere_cluster_period_and_symmetry(orc):
+    """Sec. 4: the tetrahedral four-sphere cluster sediments periodically with a
+    cycle of about 517 tau_s (Euler, dt = 0.01); x3 = -x1, z3 = z1, z4 = z2,
+    y1 = y3 = x2 = x4 = 0, and y2 = -y4."""
+    gold = json.load(open(os.path.join(GOLDEN, "four_sphere_period.json")))
+    p = orc.params()
+    x0, F = W.four_sphere_tetrahedron()
+    stride = 10
+    _, _, traj = orc.run(p, x0, F, 0.01, 120000, orc.EULER, stride=stride)
+    tol = 1e-10
+    np.testing.assert_allclose(traj[:, 2, 0], -traj[:, 0, 0], atol=tol)
+    np.testing.assert_allclose(traj[:, 2, 2], traj[:, 0, 2], atol=tol)
+    np.testing.assert_allclose(traj[:, 3, 2], traj[:, 1, 2], atol=tol)
+    np.testing.assert_allclose(traj[:, 3, 1], -traj[:, 1, 1], atol=tol)
+    for (k, c) in [(0, 1), (2, 1), (1, 0), (3, 0)]:
+        assert np.abs(traj[:, k, c]).max() < tol
+    t = np.arange(traj.shape[0]) * 0.01 * stride
+    m = _maxima(t, traj[:, 0, 0])
+    assert len(m) >= 2
+    period = np.diff(m).mean()
+    assert abs(period - gold["value"]) < gold["tolerance_abs"], period
+    # y2 follows x1 shifted by half a period
+    half = int(round(period / 2 / (0.01 * stride)))
+    i0 = int(m[0] / (0.01 * stride))
+    np.testing.assert_allclose(traj[i0 + half, 1, 1], traj[i0, 0, 0], rtol=2e-2)
+
+
+# ------------------------------------------------------------- adjoint
+
+@pytest.mark.parametrize("tensor,overlap,r", [(0, False, 2.7), (0, True, 1.2), (1, False, 3.3),
+                                              (0, False, 20.0)])
+def test_pair_gradient_finite_differences(orc, tensor, overlap, r):
+    p = orc.params(a=1.0, eta=0.4, tensor=tensor, overlap=overlap)
+    rng = np.random.default_rng(51)
+    R = r * np.array([0.6, 0.0, 0.8])
+    u, w = rng.standard_normal(3), rng.standard_normal(3)
+    g = orc.pair_grad(p, R, u, w)
+    h = 1e-6 * r
+    fd = np.zeros(3)
+    for k in range(3):
+        e = np.zeros(3)
+        e[k] = h
+        fd[k] = (u @ orc.pair_tensor(p, R + e) @ w - u @ orc.pair_tensor(p, R - e) @ w) / (2 * h)
+    np.testing.assert_allclose(g, fd, rtol=1e-7, atol=1e-9 * np.abs(g).max())
+
+
+def test_vjp_x_finite_differences(orc):
+    x = W.random_suspension(10, phi=0.1, seed=61)
+    f = W.gaussian_forces(10, seed=62)
+    lam = W.gaussian_forces(10, seed=63)
+    for p in [orc.params(), orc.params(overlap=True, a=2.0)]:
+        g = orc.mobility_vjp_x(p, x, f, lam)
+        fd = np.zeros_like(x)
+        h = 1e-6
+        for i in range(10):
+            for k in range(3):
+                xp, xm = x.copy(), x.copy()
+                xp[i, k] += h
+                xm[i, k] -= h
+                fd[i, k] = (np.sum(lam * orc.mobility(p, xp, f))
+                            - np.sum(lam * orc.mobility(p, xm, f))) / (2 * h)
+        np.testing.assert_allclose(g, fd, rtol=1e-6, atol=1e-8 * np.abs(g).max())
+
+
+def _diff_problem(n=16, steps=200, dt=0.01):
+    x0 = W.random_suspension(n, phi=0.05, seed=71)
+    F0 = W.gravity_forces(n)
+    Fp = F0 + 0.1 * W.gaussian_forces(n, seed=4)
+    return x0, F0, Fp, dt, steps
+
+
+def test_adjoint_matches_finite_differences(orc):
+    """Discrete adjoint of the Euler loop vs FP64 central differences of
+    L = |x_N - x_target|^2 (the differentiation workload at n = 16)."""
+    p = orc.params()
+    x0, F0, Fp, dt, steps = _diff_problem()
+    xt, _, _ = orc.run(p, x0, Fp, dt, steps)
+
+    def loss(x0_, F_):
+        xN, _, _ = orc.run(p, x0_, F_, dt, steps)
+        return np.sum((xN - xt) ** 2)
+
+    xN, _, _ = orc.run(p, x0, F0, dt, steps)
+    gx, gf = orc.run_adjoint_euler(p, x0, F0, dt, steps, 2 * (xN - xt))
+    fdx, fdf = np.zeros_like(x0), np.zeros_like(F0)
+    for i in range(x0.shape[0]):
+        for k in range(3):
+            for (arr, out, which) in ((x0, fdx, 0), (F0, fdf, 1)):
+                h = 1e-6 * max(1.0, abs(arr[i, k]))
+                ap, am = arr.copy(), arr.copy()
+                ap[i, k] += h
+                am[i, k] -= h
+                if which == 0:
+                    out[i, k] = (loss(ap, F0) - loss(am, F0)) / (2 * h)
+                else:
+                    out[i, k] = (loss(x0, ap) - loss(x0, am)) / (2 * h)
+    for g, fd in ((gx, fdx), (gf, fdf)):
+        assert np.linalg.norm(g - fd) <= 1e-6 * np.linalg.norm(fd)
