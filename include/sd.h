@@ -1,0 +1,256 @@
+/*
+ * sd.h -- C ABI of the MI355X (gfx950) all-pairs Stokesian-dynamics library.
+ *
+ * Computes, for N spheres of radius a in a fluid of viscosity eta, the
+ * mobility product of Eq. (7a) of Kopp & Hoefling (2012),
+ *     v_i = mu0 F_i + sum_{j != i} T(r_i - r_j) F_j,   mu0 = 1/(6 pi eta a),
+ * with the Rotne-Prager pair tensor T of Eq. (7b) or the Oseen tensor G of
+ * Eq. (4), and advances positions with it (Sec. 3.1, steps 1 and 3).  The
+ * mobility matrix is never stored (Sec. 3.1): every pair block is evaluated on
+ * the fly on the GPU.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - All array arguments are DEVICE pointers into memory owned by the caller
+ *    (e.g. PyTorch tensors), except where a parameter says "host".
+ *  - `stream` is a hipStream_t (NULL = the null stream).  Every call only
+ *    enqueues work on `stream` and returns; results are ready once the stream
+ *    has reached that point.  Calls that enqueue work on the same device and
+ *    share library workspace (see sd_release) must not run concurrently on
+ *    different streams.
+ *  - Errors are returned as sd_status; the library never aborts.  A failed
+ *    argument check enqueues nothing.  sd_last_error() gives a message for the
+ *    last failure of the calling thread.  NaN/Inf inputs are not checked; they
+ *    propagate into the results.
+ *  - Output arrays may not alias input arrays unless a parameter says so.
+ *  - Layouts:
+ *      "f32x4[n]"  n records of 4 floats  (x, y, z, w), 16-byte aligned, w ignored
+ *      "f64x4[n]"  n records of 4 doubles (x, y, z, w), 32-byte aligned, w ignored
+ *      "f64[3n]"   n records of 3 doubles (x, y, z), 8-byte aligned
+ *    Positions and forces use f32x4 for the FP32 precisions and f64x4 for
+ *    SD_FP64; velocities, time-loop positions and gradients are always f64[3n].
+ *  - Pair blocks at distance r < 2a (overlapping spheres), r = 0 for i != j
+ *    (coincident spheres) and the self term are evaluated in FP64 in every
+ *    precision.  Coincident spheres contribute mu0 F_j with the overlap form
+ *    (its r -> 0 limit) and nothing otherwise.
+ */
+#ifndef SD_H
+#define SD_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum sd_status {
+    SD_OK = 0,
+    SD_EINVAL = 1,        /* bad size, null pointer, bad parameter or enum value */
+    SD_EALIGN = 2,        /* a pointer is not aligned as its layout requires */
+    SD_ENOMEM = 3,        /* library workspace could not be allocated */
+    SD_EDEVICE = 4,       /* a HIP runtime call or kernel launch failed */
+    SD_EUNSUPPORTED = 5   /* valid arguments the library does not implement */
+} sd_status;
+
+typedef enum sd_tensor {
+    SD_RPY = 0,           /* Rotne-Prager tensor, Eq. (7b) */
+    SD_OSEEN = 1          /* Oseen tensor, Eq. (4) */
+} sd_tensor;
+
+typedef enum sd_overlap {
+    SD_OVERLAP_NONE = 0,  /* the far form of the tensor at every r > 0 */
+    SD_OVERLAP_RPY = 1    /* r < 2a: mu0[(1 - 9r/32a) I + (3r/32a) rhat rhat]
+                             (Rotne-Prager-Yamakawa regularisation; not in the
+                             paper, which defines T for r >= 2a only).
+                             Ignored for SD_OSEEN. */
+} sd_overlap;
+
+typedef enum sd_precision {
+    SD_FP32_KAHAN = 0,    /* FP32 pair evaluation, Kahan-compensated FP32
+                             per-particle accumulation (the paper's "single
+                             precision tensor, higher-precision accumulation",
+                             Sec. 3.2) */
+    SD_FP64 = 1,          /* FP64 throughout */
+    SD_FP32_PLAIN = 2     /* FP32 evaluation and plain FP32 accumulation */
+} sd_precision;
+
+typedef enum sd_integrator {
+    SD_EULER = 0,         /* x += dt v (Sec. 3.1, step 1) */
+    SD_AB2 = 1            /* x += dt (3/2 v_k - 1/2 v_{k-1}); the step with
+                             global index 0 is an Euler step (not in the paper) */
+} sd_integrator;
+
+typedef struct sd_params {
+    double a;             /* sphere radius, > 0 */
+    double eta;           /* shear viscosity, > 0 */
+    int32_t tensor;       /* sd_tensor */
+    int32_t overlap;      /* sd_overlap */
+} sd_params;
+
+/* ------------------------------------------------------------------ product */
+
+/*
+ * mobility_apply -- v = M(x) F, Eq. (7a); step 3 of the algorithm of Sec. 3.1.
+ *   n      number of particles, >= 1
+ *   pos    f32x4[n] (FP32 precisions) or f64x4[n] (SD_FP64): positions
+ *   force  same layout as pos: forces F_j
+ *   vel    f64[3n], written: velocities v_i
+ * Returns SD_EINVAL for n < 1, null pointers, a <= 0, eta <= 0 or unknown
+ * enum values; SD_EALIGN for misaligned pos/force/vel.
+ */
+sd_status mobility_apply(const sd_params* p, int64_t n, const void* pos, const void* force,
+                         double* vel, int32_t precision, void* stream);
+
+/*
+ * mobility_adjoint -- reverse-mode derivative of the product.  For a
+ * cotangent lam (dL/dv):
+ *   grad_pos   f64[3n], written: d/dx [lam . M(x) F]
+ *              = sum_{j != i} grad_r [lam_i . T(r) F_j + lam_j . T(r) F_i] at r = x_i - x_j
+ *   grad_force f64[3n], written unless NULL: M(x)^T lam = M(x) lam, by the block
+ *              symmetry mu_ij = mu_ji (Secs. 3.2, 3.3)
+ *   lam        same layout as force (f32x4[n] / f64x4[n])
+ * The gradient at r = 2a is the one-sided one of the far form; at r = 0 the
+ * pair contributes no gradient.  Errors as mobility_apply.
+ */
+sd_status mobility_adjoint(const sd_params* p, int64_t n, const void* pos, const void* force,
+                           const void* lam, double* grad_pos, double* grad_force,
+                           int32_t precision, void* stream);
+
+/* ---------------------------------------------------------------- time loop */
+
+/*
+ * sd_step -- one step of dx/dt = M(x) F with constant forces (Sec. 3.1):
+ * v_k = M(x_k) F is computed from the positions before they move, then
+ *   SD_EULER: x_{k+1} = x_k + dt v_k
+ *   SD_AB2:   x_{k+1} = x_k + dt (3/2 v_k - 1/2 v_{k-1}),  Euler if step_index == 0
+ *   x          f64[3n], in/out: FP64 master positions (the pair kernel reads an
+ *              FP32 copy; pairs closer than 2a use x directly, in FP64)
+ *   force      f32x4[n] or f64x4[n] as in mobility_apply
+ *   v_prev     f64[3n] or NULL (Euler).  AB2: in = v_{k-1} (ignored when
+ *              step_index == 0), out = v_k.  Required for AB2.
+ *   v_out      f64[3n] or NULL: receives v_k
+ *   dt > 0, step_index >= 0 (global index of this step)
+ */
+sd_status sd_step(const sd_params* p, int64_t n, double* x, const void* force, double* v_prev,
+                  double* v_out, double dt, int64_t step_index, int32_t integrator,
+                  int32_t precision, void* stream);
+
+/*
+ * sd_run -- `steps` consecutive sd_step calls with step indices step0,
+ * step0+1, ...; bitwise identical to calling sd_step that many times.
+ *   x_checkpoints  f64[(steps / checkpoint_every + 1) * 3n] or NULL: frame q
+ *                  receives x at step step0 + q * checkpoint_every (frame 0 =
+ *                  the initial x).  checkpoint_every >= 1 when non-NULL.
+ * Other arguments as sd_step.  steps == 0 is a no-op (frame 0 is still written).
+ */
+sd_status sd_run(const sd_params* p, int64_t n, double* x, const void* force, double* v_prev,
+                 double dt, int64_t steps, int64_t step0, int32_t integrator, int32_t precision,
+                 double* x_checkpoints, int64_t checkpoint_every, void* stream);
+
+/*
+ * sd_run_adjoint -- gradients of a loss L(x_steps) through `steps` Euler steps
+ * started at x0 (discrete adjoint of sd_run with SD_EULER, step0 = 0):
+ *   lam_steps = grad_xN;  lam_k = lam_{k+1} + dt d/dx[lam_{k+1} . M(x_k) F]
+ *   grad_x0 = lam_0,  grad_force = sum_k dt M(x_k) lam_{k+1}
+ *   x0            f64[3n], read only
+ *   x_checkpoints as written by sd_run(x0, ..., checkpoint_every) or NULL
+ *                 (then the library runs the forward pass itself and keeps
+ *                 every checkpoint_every-th state); each segment of
+ *                 checkpoint_every steps is recomputed from its checkpoint
+ *   grad_xN       f64[3n] (dL/dx_steps), read only
+ *   grad_x0, grad_force  f64[3n], written
+ * SD_EUNSUPPORTED for other integrators.
+ */
+sd_status sd_run_adjoint(const sd_params* p, int64_t n, const double* x0, const void* force,
+                         double dt, int64_t steps, int32_t precision, const double* x_checkpoints,
+                         int64_t checkpoint_every, const double* grad_xN, double* grad_x0,
+                         double* grad_force, void* stream);
+
+/* ------------------------------------------------------------------ batched */
+
+/* Many independent clusters: particles of different clusters do not interact
+ * (each cluster is its own free-space suspension). */
+typedef struct sd_batch sd_batch;
+
+/*
+ * sd_batch_create -- plan for n_clusters clusters; cluster c owns particles
+ * [offsets[c], offsets[c+1]).  offsets: HOST int64[n_clusters + 1],
+ * offsets[0] == 0, non-decreasing; sizes up to SD_BATCH_MAX_CLUSTER.  The plan
+ * orders clusters longest first for the persistent kernel's work queue and
+ * owns a small device buffer; it is bound to the current device.
+ */
+#define SD_BATCH_MAX_CLUSTER 1024
+sd_status sd_batch_create(const sd_params* p, int64_t n_clusters, const int64_t* offsets,
+                          sd_batch** out);
+sd_status sd_batch_destroy(sd_batch* b);
+int64_t sd_batch_particles(const sd_batch* b);
+
+/*
+ * mobility_apply_batched -- per-cluster products, layouts as mobility_apply
+ * over all sum_c N_c particles.
+ */
+sd_status mobility_apply_batched(sd_batch* b, const void* pos, const void* force, double* vel,
+                                 int32_t precision, void* stream);
+
+/*
+ * sd_run_batched -- `steps` steps of every cluster in ONE persistent kernel
+ * launch (each workgroup pulls clusters from a queue and keeps a cluster in
+ * LDS for all steps).  x f64[3 total] in/out, force f32x4[total] (FP32
+ * precisions) or f64x4[total] (SD_FP64).  use_graph != 0 launches through a
+ * captured HIP graph cached in the plan.  Step indices start at 0.
+ */
+sd_status sd_run_batched(sd_batch* b, double* x, const void* force, double dt, int64_t steps,
+                         int32_t integrator, int32_t precision, int32_t use_graph, void* stream);
+
+/* ------------------------------------------------------------------- tuning */
+
+/* Kernel shape of the all-pairs product. */
+typedef struct sd_kernel_config {
+    int32_t variant;      /* 0 = j-tiles staged in LDS, 1 = j data through the
+                             scalar cache */
+    int32_t block;        /* work-group size (64, 128 or 256) */
+    int32_t splits;       /* j-range splits (>= 1): extra work-groups per i-block */
+    int32_t ilp;          /* particles i per lane (1 or 2) */
+    int32_t kahan_block;  /* SD_FP32_KAHAN: pair terms summed in FP32 before each
+                             compensated add (1 = per term, 2 or 4); 0 for the
+                             other precisions */
+} sd_kernel_config;
+
+/* Force a configuration for a precision (NULL restores automatic choice). */
+sd_status sd_set_kernel_config(int32_t precision, const sd_kernel_config* cfg);
+/* The configuration mobility_apply would use for n particles. */
+sd_status sd_get_kernel_config(int32_t precision, int64_t n, sd_kernel_config* out);
+
+/*
+ * sd_autotune -- time candidate configurations on n synthetic particles and
+ * install the fastest for that precision and size class.  report (host
+ * buffer, may be NULL) receives a JSON summary, truncated to report_len.
+ * Synchronises the stream; allocates temporary device memory.
+ */
+sd_status sd_autotune(const sd_params* p, int64_t n, int32_t precision, void* stream,
+                      char* report, int64_t report_len);
+
+/* ---------------------------------------------------------------- profiling */
+
+/* When enabled, the library brackets every launch of its pair kernel with HIP
+ * events on the launch stream and accumulates the elapsed times. */
+sd_status sd_profile_enable(int32_t on);
+/* Pair-kernel launches and their total time since the last reset (waits for
+ * the recorded events). */
+sd_status sd_profile_read(int64_t* launches, double* total_ms);
+sd_status sd_profile_reset(void);
+
+/* --------------------------------------------------------------------- misc */
+
+/* Frees library-owned device workspace on every device (staging copies,
+ * split partials).  Safe to call at any time when no library work is pending. */
+sd_status sd_release(void);
+const char* sd_status_string(int32_t status);
+const char* sd_last_error(void);
+int32_t sd_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SD_H */

@@ -62,8 +62,15 @@ def _load():
         lib.oracle_mobility_vjp_x.argtypes = [P, i64, d, d, d, d]
         lib.oracle_run_adjoint_euler.argtypes = [P, i64, d, d, ctypes.c_double, i64, d, d, d]
         lib.oracle_run_adjoint_euler.restype = ctypes.c_int
+        lib.oracle_threads.argtypes = []
+        lib.oracle_threads.restype = ctypes.c_int
         _lib = lib
     return _lib
+
+
+def threads() -> int:
+    """Threads the oracle's parallel loops use."""
+    return int(_load().oracle_threads())
 
 
 def params(a: float = 1.0, eta: float = 1.0 / (6.0 * np.pi), tensor: int = RPY,

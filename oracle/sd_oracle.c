@@ -27,6 +27,9 @@
  *     the positions move (standard explicit Euler).
  */
 #include <math.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 #include <stddef.h>
 #include <stdint.h>
 #include <stdlib.h>
@@ -40,6 +43,16 @@ typedef struct {
 } oracle_params;
 
 enum { OR_RPY = 0, OR_OSEEN = 1 };
+
+/* Number of threads the parallel loops below run on (1 without OpenMP). */
+int oracle_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
 
 /* Stokes mobility of a single sphere, mu0 = 1/(6 pi eta a): Eq. (7a), Sec. 2.2. */
 static double stokes_mobility(const oracle_params* p)

@@ -1,7 +1,14 @@
 """MI355X-native all-pairs Stokesian-dynamics mobility product (HIP, gfx950).
 
-The compute path lives in the HIP shared library built from ``csrc/``; the
-Python functions here only marshal arguments to its C ABI.  Importing the
+The compute path lives in the HIP shared library libsd.so built from
+``csrc/`` (``python -m paper_1205_6333_amd.build``); the functions exported
+here only marshal arguments to its C ABI (include/sd.h).  Importing the
 package does not load the library; the first call does, and fails loudly if
-the library is missing.
+the library is missing.  Seeded synthetic inputs are in ``workloads``.
 """
+from .binding import (SD_AB2, SD_EULER, SD_FP32_KAHAN, SD_FP32_PLAIN, SD_FP64, SD_OSEEN,  # noqa
+                      SD_OVERLAP_NONE, SD_OVERLAP_RPY, SD_RPY, Batch, SdError, lib,
+                      mobility_adjoint, mobility_apply, mobility_apply_batched, params,
+                      sd_autotune, sd_get_kernel_config, sd_profile_enable, sd_profile_read,
+                      sd_profile_reset, sd_release, sd_run, sd_run_adjoint, sd_run_batched,
+                      sd_set_kernel_config, sd_step, sd_version)

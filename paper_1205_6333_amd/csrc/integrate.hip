@@ -1,0 +1,174 @@
+// integrate.hip -- O(N) kernels of the time loop (Sec. 3.1, step 1) and small
+// helpers: FP64 -> FP32 staging of positions, split merge fused with the
+// Euler / AB2 position update, packing and axpy for the adjoint loop.
+#include "sd_internal.h"
+
+namespace sd {
+
+__global__ void __launch_bounds__(256) k_stage_f32(const double* __restrict__ x,
+                                                   float4* __restrict__ pos, int n)
+{
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    pos[i] = make_float4((float)x[3 * (size_t)i], (float)x[3 * (size_t)i + 1],
+                         (float)x[3 * (size_t)i + 2], 0.0f);
+}
+
+__global__ void __launch_bounds__(256) k_stage_f64(const double* __restrict__ x,
+                                                   double4* __restrict__ pos, int n)
+{
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    pos[i] = make_double4(x[3 * (size_t)i], x[3 * (size_t)i + 1], x[3 * (size_t)i + 2], 0.0);
+}
+
+__device__ __forceinline__ void put_pos(float4* p, int i, double a, double b, double c)
+{
+    p[i] = make_float4((float)a, (float)b, (float)c, 0.0f);
+}
+__device__ __forceinline__ void put_pos(double4* p, int i, double a, double b, double c)
+{
+    p[i] = make_double4(a, b, c, 0.0);
+}
+
+// v_k = mu0 F + sum_s partial_s (the same order as k_merge), then
+//   mode 0: x += dt v                       (Euler)
+//   mode 1: x += dt v,  v_prev = v           (first AB2 step)
+//   mode 2: x += dt (3/2 v - 1/2 v_prev), v_prev = v   (AB2)
+// and the staged copy of the new positions for the next pair kernel.
+template <typename F4, typename P4>
+__global__ void __launch_bounds__(256)
+k_merge_integrate(const double* __restrict__ partial, int S, int n, const F4* __restrict__ frc,
+                  double mu0, double* __restrict__ x, double* __restrict__ v_prev,
+                  double* __restrict__ v_out, double dt, int mode, P4* __restrict__ pos_next)
+{
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    const F4 f = frc[i];
+    double v[3] = { mu0 * (double)f.x, mu0 * (double)f.y, mu0 * (double)f.z };
+    for (int s = 0; s < S; ++s) {
+        const size_t base = (size_t)s * 3 * (size_t)n + (size_t)i;
+        v[0] += partial[base];
+        v[1] += partial[base + (size_t)n];
+        v[2] += partial[base + 2 * (size_t)n];
+    }
+    double xn[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const size_t e = 3 * (size_t)i + k;
+        const double inc = (mode == 2) ? (1.5 * v[k] - 0.5 * v_prev[e]) : v[k];
+        xn[k] = x[e] + dt * inc;
+        x[e] = xn[k];
+        if (mode != 0) v_prev[e] = v[k];
+        if (v_out) v_out[e] = v[k];
+    }
+    if (pos_next) put_pos(pos_next, i, xn[0], xn[1], xn[2]);
+}
+
+__global__ void __launch_bounds__(256) k_sum_partials(const double* __restrict__ partial, int S,
+                                                      int n, double* __restrict__ out,
+                                                      double scale, int accumulate)
+{
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    double g[3] = { 0.0, 0.0, 0.0 };
+    for (int s = 0; s < S; ++s) {
+        const size_t base = (size_t)s * 3 * (size_t)n + (size_t)i;
+        g[0] += partial[base];
+        g[1] += partial[base + (size_t)n];
+        g[2] += partial[base + 2 * (size_t)n];
+    }
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const size_t e = 3 * (size_t)i + k;
+        out[e] = accumulate ? out[e] + scale * g[k] : scale * g[k];
+    }
+}
+
+template <typename P4>
+__global__ void __launch_bounds__(256) k_pack(const double* __restrict__ v, P4* __restrict__ out,
+                                              int n)
+{
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    put_pos(out, i, v[3 * (size_t)i], v[3 * (size_t)i + 1], v[3 * (size_t)i + 2]);
+}
+
+__global__ void __launch_bounds__(256) k_axpy(double s, const double* __restrict__ x,
+                                              double* __restrict__ y, int64_t m)
+{
+    const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (k < m) y[k] += s * x[k];
+}
+
+__global__ void __launch_bounds__(64) k_fill_i32(int32_t* __restrict__ p, int32_t value, int count)
+{
+    const int k = blockIdx.x * 64 + threadIdx.x;
+    if (k < count) p[k] = value;
+}
+
+static inline dim3 grid_for(int64_t n) { return dim3((unsigned)((n + 255) / 256)); }
+
+hipError_t launch_stage_f32(const double* x, float4* pos, int n, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_stage_f32, grid_for(n), dim3(256), 0, st, x, pos, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_stage_f64(const double* x, double4* pos, int n, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_stage_f64, grid_for(n), dim3(256), 0, st, x, pos, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_merge_integrate_f32(const double* partial, int splits, int n, const float4* frc,
+                                      double mu0, double* x, double* v_prev, double* v_out,
+                                      double dt, int mode, float4* pos_next, hipStream_t st)
+{
+    hipLaunchKernelGGL((k_merge_integrate<float4, float4>), grid_for(n), dim3(256), 0, st, partial,
+                       splits, n, frc, mu0, x, v_prev, v_out, dt, mode, pos_next);
+    return hipGetLastError();
+}
+
+hipError_t launch_merge_integrate_f64(const double* partial, int splits, int n, const double4* frc,
+                                      double mu0, double* x, double* v_prev, double* v_out,
+                                      double dt, int mode, double4* pos_next, hipStream_t st)
+{
+    hipLaunchKernelGGL((k_merge_integrate<double4, double4>), grid_for(n), dim3(256), 0, st,
+                       partial, splits, n, frc, mu0, x, v_prev, v_out, dt, mode, pos_next);
+    return hipGetLastError();
+}
+
+hipError_t launch_sum_partials(const double* partial, int splits, int n, double* out, double scale,
+                               int accumulate, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_sum_partials, grid_for(n), dim3(256), 0, st, partial, splits, n, out,
+                       scale, accumulate);
+    return hipGetLastError();
+}
+
+hipError_t launch_pack_f32(const double* v, float4* out, int n, hipStream_t st)
+{
+    hipLaunchKernelGGL((k_pack<float4>), grid_for(n), dim3(256), 0, st, v, out, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_pack_f64(const double* v, double4* out, int n, hipStream_t st)
+{
+    hipLaunchKernelGGL((k_pack<double4>), grid_for(n), dim3(256), 0, st, v, out, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_axpy(double s, const double* x, double* y, int64_t m, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_axpy, grid_for(m), dim3(256), 0, st, s, x, y, m);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_i32(int32_t* p, int32_t value, int count, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_fill_i32, dim3((count + 63) / 64), dim3(64), 0, st, p, value, count);
+    return hipGetLastError();
+}
+
+}  // namespace sd

@@ -1,0 +1,564 @@
+// mobility.hip -- all-pairs mobility product v_i = mu0 F_i + sum_{j != i} T(r_i - r_j) F_j
+// (Eq. 7a; tensors of Eq. 4 and Eq. 7b), hand-written for gfx950.
+//
+// Work decomposition: one lane owns one (or ILP) particle(s) i and walks a
+// contiguous j-range; the j-range of all N particles is cut into `splits`
+// chunks so that N = 65536 still puts several waves on every SIMD.  Each
+// (i, split) writes one FP64 partial per component; a merge kernel adds the
+// self term mu0 F_i and the partials in a fixed order (deterministic, no
+// atomics).
+//
+// Precision: the far-field pair term is evaluated in FP32 (v_rsq_f32 on the
+// VALU) and accumulated with Kahan compensation in FP32; pairs with
+// r^2 < (2a)^2 (1 + NEAR_EPS), the self pair and coincident spheres are
+// evaluated in FP64 on a rarely taken branch.  SD_FP64 runs the same loop in
+// double.
+#include "sd_internal.h"
+
+#include <cmath>
+
+namespace sd {
+
+PairConst make_pair_const(double a, double eta, int tensor, int overlap)
+{
+    PairConst c;
+    const double gamma = (tensor == T_RPY) ? 2.0 * a * a / 3.0 : 0.0;
+    const double thr2 = 4.0 * a * a * (1.0 + NEAR_EPS);
+    c.gamma_f = (float)gamma;
+    c.m3gamma_f = (float)(-3.0 * gamma);
+    c.thr2_f = (float)thr2;
+    c.overlap = (tensor == T_RPY && overlap) ? 1 : 0;
+    c.thr2_d = thr2;
+    c.alpha = 1.0 / (8.0 * M_PI * eta);
+    c.gamma = gamma;
+    c.mu0 = 1.0 / (6.0 * M_PI * eta * a);
+    c.a = a;
+    return c;
+}
+
+PairLaunch shape_pair_launch(int n, int variant, int block, int splits, int ilp)
+{
+    PairLaunch L;
+    L.variant = variant;
+    L.block = block;
+    L.ilp = ilp;
+    if (splits < 1) splits = 1;
+    // j chunks are whole tiles of `block` particles
+    const int tiles = (n + block - 1) / block;
+    if (splits > tiles) splits = tiles;
+    const int tiles_per = (tiles + splits - 1) / splits;
+    L.jchunk = tiles_per * block;
+    L.splits = (n + L.jchunk - 1) / L.jchunk;
+    return L;
+}
+
+// Placeholders for padded lanes / padded tile slots.  Far apart, zero force:
+// every term they produce is exactly zero or never stored, and never NaN.
+#define SD_FAR_I (-1.0e15f)
+#define SD_FAR_J (1.0e15f)
+
+// FP64 contribution of one near pair (d = x_i - x_j, r^2 below threshold) to v_i.
+template <int TENSOR>
+__device__ __forceinline__ void near_term(const PairConst& pc, double d0, double d1, double d2,
+                                          double f0, double f1, double f2, double& n0, double& n1,
+                                          double& n2)
+{
+    const double r2 = d0 * d0 + d1 * d1 + d2 * d2;
+    if (r2 == 0.0) {  // coincident distinct spheres: limit of the overlap form, else nothing
+        if (TENSOR == T_RPY && pc.overlap) {
+            n0 += pc.mu0 * f0;
+            n1 += pc.mu0 * f1;
+            n2 += pc.mu0 * f2;
+        }
+        return;
+    }
+    const double r = sqrt(r2);
+    double cI, cD;  // T = cI I + cD d d
+    if (TENSOR == T_OSEEN) {
+        cI = pc.alpha / r;
+        cD = cI / r2;
+    } else if (pc.overlap && r < 2.0 * pc.a) {
+        cI = pc.mu0 * (1.0 - 9.0 * r / (32.0 * pc.a));
+        cD = pc.mu0 * 3.0 / (32.0 * pc.a * r);
+    } else {
+        const double ri = 1.0 / r, ri2 = ri * ri, ri3 = ri * ri2;
+        cI = pc.alpha * (ri + pc.gamma * ri3);
+        cD = pc.alpha * ri3 * (1.0 - 3.0 * pc.gamma * ri2);
+    }
+    const double dF = d0 * f0 + d1 * f1 + d2 * f2;
+    n0 += cI * f0 + cD * dF * d0;
+    n1 += cI * f1 + cD * dF * d1;
+    n2 += cI * f2 + cD * dF * d2;
+}
+
+// Per-lane state of one particle i.
+struct LaneF32 {
+    float x, y, z;        // position (FP32)
+    float s0, s1, s2;     // running sums (scaled units)
+    float c0, c1, c2;     // Kahan compensations
+    double n0, n1, n2;    // FP64 near-pair sums (physical units)
+    int i;
+};
+
+// One pair (i, j) on the FP32 fast path.  pj/fj: position and force of j
+// (wave-uniform).  jg: global index of j, used only on the near branch.
+template <int TENSOR, bool KAHAN>
+__device__ __forceinline__ void pair_f32(LaneF32& L, const float4 pj, const float4 fj, int jg,
+                                         int n, const PairConst& pc, float gamma, float m3g,
+                                         float thr2, const double* __restrict__ x64)
+{
+    const float dx = L.x - pj.x;
+    const float dy = L.y - pj.y;
+    const float dz = L.z - pj.z;
+    const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+    const bool nr = r2 < thr2;
+    float rinv = __builtin_amdgcn_rsqf(r2);
+    rinv = nr ? 0.0f : rinv;
+    const float rinv2 = rinv * rinv;
+    const float rinv3 = rinv2 * rinv;
+    float A, Bt;
+    if (TENSOR == T_OSEEN) {
+        A = rinv;
+        Bt = rinv3;
+    } else {
+        A = fmaf(gamma, rinv3, rinv);
+        Bt = rinv3 * fmaf(m3g, rinv2, 1.0f);
+    }
+    const float dF = fmaf(dx, fj.x, fmaf(dy, fj.y, dz * fj.z));
+    const float sB = Bt * dF;
+    if (KAHAN) {
+        // y = term - c, t = s + y, c = (t - s) - y, s = t
+        const float y0 = fmaf(A, fj.x, fmaf(sB, dx, -L.c0));
+        const float y1 = fmaf(A, fj.y, fmaf(sB, dy, -L.c1));
+        const float y2 = fmaf(A, fj.z, fmaf(sB, dz, -L.c2));
+        const float t0 = L.s0 + y0;
+        const float t1 = L.s1 + y1;
+        const float t2 = L.s2 + y2;
+        L.c0 = (t0 - L.s0) - y0;
+        L.c1 = (t1 - L.s1) - y1;
+        L.c2 = (t2 - L.s2) - y2;
+        L.s0 = t0;
+        L.s1 = t1;
+        L.s2 = t2;
+    } else {
+        L.s0 = fmaf(A, fj.x, fmaf(sB, dx, L.s0));
+        L.s1 = fmaf(A, fj.y, fmaf(sB, dy, L.s1));
+        L.s2 = fmaf(A, fj.z, fmaf(sB, dz, L.s2));
+    }
+    // padded lanes (i >= n) and padded tile slots (j >= n) never reach the FP64
+    // evaluation: their placeholders are far from every particle, and the
+    // index test below keeps x64 reads in bounds even for absurd inputs
+    if (nr) {
+        if (jg != L.i && L.i < n && jg < n) {
+            double d0, d1, d2;
+            if (x64) {
+                d0 = x64[3 * (size_t)L.i + 0] - x64[3 * (size_t)jg + 0];
+                d1 = x64[3 * (size_t)L.i + 1] - x64[3 * (size_t)jg + 1];
+                d2 = x64[3 * (size_t)L.i + 2] - x64[3 * (size_t)jg + 2];
+            } else {
+                d0 = (double)L.x - (double)pj.x;
+                d1 = (double)L.y - (double)pj.y;
+                d2 = (double)L.z - (double)pj.z;
+            }
+            near_term<TENSOR>(pc, d0, d1, d2, (double)fj.x, (double)fj.y, (double)fj.z, L.n0,
+                              L.n1, L.n2);
+        }
+    }
+}
+
+// A group of U pairs (i, j_0..j_{U-1}) for every lane particle.  The near test
+// is done once per group: if no lane of the wave has a pair below the
+// threshold, the unmasked fast path runs; otherwise every pair of the group
+// takes the masked path (pair_f32), which also handles the self pair.
+// ACC: 0 = plain FP32 sums, k >= 1 = Kahan compensation applied once per k
+// consecutive terms (k = 1: per term).
+template <int TENSOR, int ACC, int U, int ILP>
+__device__ __forceinline__ void pair_group(LaneF32 (&L)[ILP], const float4 (&pj)[U],
+                                           const float4 (&fj)[U], int jg0, int n,
+                                           const PairConst& pc,
+                                           float gamma, float m3g, float thr2,
+                                           const double* __restrict__ x64)
+{
+    float dx[ILP][U], dy[ILP][U], dz[ILP][U], r2[ILP][U];
+    float rmin = 3.0e38f;
+#pragma unroll
+    for (int q = 0; q < ILP; ++q)
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            dx[q][u] = L[q].x - pj[u].x;
+            dy[q][u] = L[q].y - pj[u].y;
+            dz[q][u] = L[q].z - pj[u].z;
+            r2[q][u] = fmaf(dx[q][u], dx[q][u], fmaf(dy[q][u], dy[q][u], dz[q][u] * dz[q][u]));
+            rmin = fminf(rmin, r2[q][u]);
+        }
+    if (__builtin_amdgcn_ballot_w64(rmin < thr2) != 0) {
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int q = 0; q < ILP; ++q)
+                pair_f32<TENSOR, ACC != 0>(L[q], pj[u], fj[u], jg0 + u, n, pc, gamma, m3g, thr2,
+                                           x64);
+        return;
+    }
+#pragma unroll
+    for (int q = 0; q < ILP; ++q) {
+        constexpr int KB = ACC > 0 ? ACC : 1;
+#pragma unroll
+        for (int u0 = 0; u0 < U; u0 += KB) {
+            float y0 = ACC ? -L[q].c0 : L[q].s0;
+            float y1 = ACC ? -L[q].c1 : L[q].s1;
+            float y2 = ACC ? -L[q].c2 : L[q].s2;
+#pragma unroll
+            for (int u = u0; u < u0 + KB; ++u) {
+                const float rinv = __builtin_amdgcn_rsqf(r2[q][u]);
+                const float rinv2 = rinv * rinv;
+                const float rinv3 = rinv2 * rinv;
+                float A, Bt;
+                if (TENSOR == T_OSEEN) {
+                    A = rinv;
+                    Bt = rinv3;
+                } else {
+                    A = fmaf(gamma, rinv3, rinv);
+                    Bt = rinv3 * fmaf(m3g, rinv2, 1.0f);
+                }
+                const float dF = fmaf(dx[q][u], fj[u].x, fmaf(dy[q][u], fj[u].y, dz[q][u] * fj[u].z));
+                const float sB = Bt * dF;
+                y0 = fmaf(A, fj[u].x, fmaf(sB, dx[q][u], y0));
+                y1 = fmaf(A, fj[u].y, fmaf(sB, dy[q][u], y1));
+                y2 = fmaf(A, fj[u].z, fmaf(sB, dz[q][u], y2));
+            }
+            if (ACC) {
+                const float t0 = L[q].s0 + y0;
+                const float t1 = L[q].s1 + y1;
+                const float t2 = L[q].s2 + y2;
+                L[q].c0 = (t0 - L[q].s0) - y0;
+                L[q].c1 = (t1 - L[q].s1) - y1;
+                L[q].c2 = (t2 - L[q].s2) - y2;
+                L[q].s0 = t0;
+                L[q].s1 = t1;
+                L[q].s2 = t2;
+            } else {
+                L[q].s0 = y0;
+                L[q].s1 = y1;
+                L[q].s2 = y2;
+            }
+        }
+    }
+}
+
+template <int ILP, int BLOCK>
+__device__ __forceinline__ void lanes_init(LaneF32 (&L)[ILP], const float4* __restrict__ pos, int n)
+{
+    const int ibase = blockIdx.x * (BLOCK * ILP) + threadIdx.x;
+#pragma unroll
+    for (int q = 0; q < ILP; ++q) {
+        const int i = ibase + q * BLOCK;
+        L[q].i = i;
+        if (i < n) {
+            const float4 p = pos[i];
+            L[q].x = p.x;
+            L[q].y = p.y;
+            L[q].z = p.z;
+        } else {
+            L[q].x = L[q].y = L[q].z = SD_FAR_I;
+        }
+        L[q].s0 = L[q].s1 = L[q].s2 = 0.0f;
+        L[q].c0 = L[q].c1 = L[q].c2 = 0.0f;
+        L[q].n0 = L[q].n1 = L[q].n2 = 0.0;
+    }
+}
+
+template <int ILP>
+__device__ __forceinline__ void lanes_store(const LaneF32 (&L)[ILP], int n, int s, double alpha,
+                                            double* __restrict__ partial)
+{
+#pragma unroll
+    for (int q = 0; q < ILP; ++q) {
+        const int i = L[q].i;
+        if (i < n) {
+            const size_t base = (size_t)s * 3 * (size_t)n + (size_t)i;
+            partial[base] = alpha * ((double)L[q].s0 - (double)L[q].c0) + L[q].n0;
+            partial[base + (size_t)n] = alpha * ((double)L[q].s1 - (double)L[q].c1) + L[q].n1;
+            partial[base + 2 * (size_t)n] = alpha * ((double)L[q].s2 - (double)L[q].c2) + L[q].n2;
+        }
+    }
+}
+
+constexpr int GROUP_U = 4;
+
+// Variant 0: the work-group stages tiles of BLOCK j-particles (position and
+// force, 32 B each) in LDS with coalesced 16-byte loads; the next tile is
+// fetched into registers while the current one is consumed.  Every lane then
+// reads each j from LDS by broadcast.
+template <int TENSOR, int ACC, int BLOCK, int ILP>
+__global__ void __launch_bounds__(BLOCK)
+k_pair_f32_lds(const float4* __restrict__ pos, const float4* __restrict__ frc,
+               const double* __restrict__ x64, int n, int jchunk, PairConst pc,
+               double* __restrict__ partial)
+{
+    __shared__ float4 s_pos[BLOCK];
+    __shared__ float4 s_frc[BLOCK];
+    LaneF32 L[ILP];
+    lanes_init<ILP, BLOCK>(L, pos, n);
+    const int tid = threadIdx.x;
+    const int s = blockIdx.y;
+    const int jbeg = s * jchunk;
+    const int jend = min(n, jbeg + jchunk);
+    const float gamma = pc.gamma_f, m3g = pc.m3gamma_f, thr2 = pc.thr2_f;
+    const float4 far_j = make_float4(SD_FAR_J, SD_FAR_J, SD_FAR_J, 0.0f);
+    const float4 zero4 = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+
+    float4 rp = far_j, rf = zero4;
+    if (jbeg + tid < jend) {
+        rp = pos[jbeg + tid];
+        rf = frc[jbeg + tid];
+    }
+    for (int jt = jbeg; jt < jend; jt += BLOCK) {
+        __syncthreads();
+        s_pos[tid] = rp;
+        s_frc[tid] = rf;
+        __syncthreads();
+        const int jn = jt + BLOCK + tid;
+        rp = far_j;
+        rf = zero4;
+        if (jn < jend) {
+            rp = pos[jn];
+            rf = frc[jn];
+        }
+        for (int k = 0; k < BLOCK; k += GROUP_U) {
+            float4 pj[GROUP_U], fj[GROUP_U];
+#pragma unroll
+            for (int u = 0; u < GROUP_U; ++u) {
+                pj[u] = s_pos[k + u];
+                fj[u] = s_frc[k + u];
+            }
+            pair_group<TENSOR, ACC, GROUP_U, ILP>(L, pj, fj, jt + k, n, pc, gamma, m3g, thr2,
+                                                  x64);
+        }
+    }
+    lanes_store<ILP>(L, n, s, pc.alpha, partial);
+}
+
+// Variant 1: no LDS.  The j index is wave-uniform, so positions and forces of
+// j are fetched with scalar loads through the scalar cache (the paper's
+// "naive" cache-based read of Sec. 3.2, on AMD's scalar path) and enter the
+// VALU as SGPR operands.
+template <int TENSOR, int ACC, int BLOCK, int ILP>
+__global__ void __launch_bounds__(BLOCK)
+k_pair_f32_smem(const float4* __restrict__ pos, const float4* __restrict__ frc,
+                const double* __restrict__ x64, int n, int jchunk, PairConst pc,
+                double* __restrict__ partial)
+{
+    LaneF32 L[ILP];
+    lanes_init<ILP, BLOCK>(L, pos, n);
+    const int s = blockIdx.y;
+    const int jbeg = s * jchunk;
+    const int jend = min(n, jbeg + jchunk);
+    const float gamma = pc.gamma_f, m3g = pc.m3gamma_f, thr2 = pc.thr2_f;
+    int j = jbeg;
+    for (; j + GROUP_U <= jend; j += GROUP_U) {
+        float4 pj[GROUP_U], fj[GROUP_U];
+#pragma unroll
+        for (int u = 0; u < GROUP_U; ++u) {
+            pj[u] = pos[j + u];
+            fj[u] = frc[j + u];
+        }
+        pair_group<TENSOR, ACC, GROUP_U, ILP>(L, pj, fj, j, n, pc, gamma, m3g, thr2, x64);
+    }
+    for (; j < jend; ++j) {
+        const float4 pj = pos[j];
+        const float4 fj = frc[j];
+#pragma unroll
+        for (int q = 0; q < ILP; ++q)
+            pair_f32<TENSOR, ACC != 0>(L[q], pj, fj, j, n, pc, gamma, m3g, thr2, x64);
+    }
+    lanes_store<ILP>(L, n, s, pc.alpha, partial);
+}
+
+// ---------------------------------------------------------------- FP64 path
+
+template <int TENSOR, int BLOCK>
+__global__ void __launch_bounds__(BLOCK)
+k_pair_f64_lds(const double4* __restrict__ pos, const double4* __restrict__ frc, int n, int jchunk,
+               PairConst pc, double* __restrict__ partial)
+{
+    __shared__ double4 s_pos[BLOCK];
+    __shared__ double4 s_frc[BLOCK];
+    const int tid = threadIdx.x;
+    const int i = blockIdx.x * BLOCK + tid;
+    const int s = blockIdx.y;
+    double xi0 = -1.0e15, xi1 = -1.0e15, xi2 = -1.0e15;
+    if (i < n) {
+        const double4 p = pos[i];
+        xi0 = p.x;
+        xi1 = p.y;
+        xi2 = p.z;
+    }
+    double v0 = 0.0, v1 = 0.0, v2 = 0.0;  // scaled far-field sums
+    double n0 = 0.0, n1 = 0.0, n2 = 0.0;  // near sums (physical units)
+    const int jbeg = s * jchunk;
+    const int jend = min(n, jbeg + jchunk);
+    const double gamma = pc.gamma, m3g = -3.0 * pc.gamma, thr2 = pc.thr2_d;
+    const double4 far_j = make_double4(1.0e15, 1.0e15, 1.0e15, 0.0);
+    const double4 zero4 = make_double4(0.0, 0.0, 0.0, 0.0);
+    double4 rp = far_j, rf = zero4;
+    if (jbeg + tid < jend) {
+        rp = pos[jbeg + tid];
+        rf = frc[jbeg + tid];
+    }
+    for (int jt = jbeg; jt < jend; jt += BLOCK) {
+        __syncthreads();
+        s_pos[tid] = rp;
+        s_frc[tid] = rf;
+        __syncthreads();
+        const int jn = jt + BLOCK + tid;
+        rp = far_j;
+        rf = zero4;
+        if (jn < jend) {
+            rp = pos[jn];
+            rf = frc[jn];
+        }
+#pragma unroll 2
+        for (int k = 0; k < BLOCK; ++k) {
+            const double4 pj = s_pos[k];
+            const double4 fj = s_frc[k];
+            const double dx = xi0 - pj.x, dy = xi1 - pj.y, dz = xi2 - pj.z;
+            const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
+            const bool nr = r2 < thr2;
+            double rinv = rsqrt(r2);
+            rinv = nr ? 0.0 : rinv;
+            const double rinv2 = rinv * rinv;
+            const double rinv3 = rinv2 * rinv;
+            double A, Bt;
+            if (TENSOR == T_OSEEN) {
+                A = rinv;
+                Bt = rinv3;
+            } else {
+                A = fma(gamma, rinv3, rinv);
+                Bt = rinv3 * fma(m3g, rinv2, 1.0);
+            }
+            const double sB = Bt * fma(dx, fj.x, fma(dy, fj.y, dz * fj.z));
+            v0 = fma(A, fj.x, fma(sB, dx, v0));
+            v1 = fma(A, fj.y, fma(sB, dy, v1));
+            v2 = fma(A, fj.z, fma(sB, dz, v2));
+            if (nr && (jt + k) != i && i < n && (jt + k) < n) near_term<TENSOR>(pc, dx, dy, dz, fj.x, fj.y, fj.z, n0, n1, n2);
+        }
+    }
+    if (i < n) {
+        const size_t base = (size_t)s * 3 * (size_t)n + (size_t)i;
+        partial[base] = pc.alpha * v0 + n0;
+        partial[base + (size_t)n] = pc.alpha * v1 + n1;
+        partial[base + 2 * (size_t)n] = pc.alpha * v2 + n2;
+    }
+}
+
+// ------------------------------------------------------------------ merge
+
+template <typename F4>
+__global__ void __launch_bounds__(256)
+k_merge(const double* __restrict__ partial, int S, int n, const F4* __restrict__ frc, double mu0,
+        double* __restrict__ vel)
+{
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    const F4 f = frc[i];
+    double v0 = mu0 * (double)f.x, v1 = mu0 * (double)f.y, v2 = mu0 * (double)f.z;
+    for (int s = 0; s < S; ++s) {
+        const size_t base = (size_t)s * 3 * (size_t)n + (size_t)i;
+        v0 += partial[base];
+        v1 += partial[base + (size_t)n];
+        v2 += partial[base + 2 * (size_t)n];
+    }
+    vel[3 * (size_t)i + 0] = v0;
+    vel[3 * (size_t)i + 1] = v1;
+    vel[3 * (size_t)i + 2] = v2;
+}
+
+// ---------------------------------------------------------------- launchers
+
+template <int TENSOR, int ACC, int BLOCK, int ILP>
+static hipError_t launch_f32_t(const PairLaunch& L, const float4* pos, const float4* frc,
+                               const double* x64, int n, const PairConst& pc, double* partial,
+                               hipStream_t st)
+{
+    const int iblocks = (n + BLOCK * ILP - 1) / (BLOCK * ILP);
+    dim3 grid(iblocks, L.splits), block(BLOCK);
+    if (L.variant == 1)
+        hipLaunchKernelGGL((k_pair_f32_smem<TENSOR, ACC, BLOCK, ILP>), grid, block, 0, st, pos,
+                           frc, x64, n, L.jchunk, pc, partial);
+    else
+        hipLaunchKernelGGL((k_pair_f32_lds<TENSOR, ACC, BLOCK, ILP>), grid, block, 0, st, pos,
+                           frc, x64, n, L.jchunk, pc, partial);
+    return hipGetLastError();
+}
+
+template <int TENSOR, int ACC>
+static hipError_t launch_f32_b(const PairLaunch& L, const float4* pos, const float4* frc,
+                               const double* x64, int n, const PairConst& pc, double* partial,
+                               hipStream_t st)
+{
+#define SD_CASE(B, I)                                                                        \
+    if (L.block == B && L.ilp == I)                                                          \
+        return launch_f32_t<TENSOR, ACC, B, I>(L, pos, frc, x64, n, pc, partial, st);
+    SD_CASE(64, 1) SD_CASE(128, 1) SD_CASE(256, 1)
+    SD_CASE(64, 2) SD_CASE(128, 2) SD_CASE(256, 2)
+#undef SD_CASE
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_pair_f32(const PairLaunch& L, int tensor, int acc, const float4* pos,
+                           const float4* frc, const double* x64, int n, const PairConst& pc,
+                           double* partial, hipStream_t st)
+{
+#define SD_ACC(T)                                                                    \
+    switch (acc) {                                                                   \
+    case 0: return launch_f32_b<T, 0>(L, pos, frc, x64, n, pc, partial, st);         \
+    case 1: return launch_f32_b<T, 1>(L, pos, frc, x64, n, pc, partial, st);         \
+    case 2: return launch_f32_b<T, 2>(L, pos, frc, x64, n, pc, partial, st);         \
+    case 4: return launch_f32_b<T, 4>(L, pos, frc, x64, n, pc, partial, st);         \
+    default: return hipErrorInvalidValue;                                            \
+    }
+    if (tensor == T_OSEEN) { SD_ACC(T_OSEEN) }
+    SD_ACC(T_RPY)
+#undef SD_ACC
+}
+
+template <int TENSOR, int BLOCK>
+static hipError_t launch_f64_t(const PairLaunch& L, const double4* pos, const double4* frc, int n,
+                               const PairConst& pc, double* partial, hipStream_t st)
+{
+    dim3 grid((n + BLOCK - 1) / BLOCK, L.splits), block(BLOCK);
+    hipLaunchKernelGGL((k_pair_f64_lds<TENSOR, BLOCK>), grid, block, 0, st, pos, frc, n, L.jchunk,
+                       pc, partial);
+    return hipGetLastError();
+}
+
+hipError_t launch_pair_f64(const PairLaunch& L, int tensor, const double4* pos, const double4* frc,
+                           int n, const PairConst& pc, double* partial, hipStream_t st)
+{
+#define SD_CASE(B)                                                                           \
+    if (L.block == B)                                                                        \
+        return tensor == T_OSEEN ? launch_f64_t<T_OSEEN, B>(L, pos, frc, n, pc, partial, st) \
+                                 : launch_f64_t<T_RPY, B>(L, pos, frc, n, pc, partial, st);
+    SD_CASE(64) SD_CASE(128) SD_CASE(256) SD_CASE(512)
+#undef SD_CASE
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_merge_f32(const double* partial, int splits, int n, const float4* frc, double mu0,
+                            double* vel, hipStream_t st)
+{
+    hipLaunchKernelGGL((k_merge<float4>), dim3((n + 255) / 256), dim3(256), 0, st, partial, splits,
+                       n, frc, mu0, vel);
+    return hipGetLastError();
+}
+
+hipError_t launch_merge_f64(const double* partial, int splits, int n, const double4* frc,
+                            double mu0, double* vel, hipStream_t st)
+{
+    hipLaunchKernelGGL((k_merge<double4>), dim3((n + 255) / 256), dim3(256), 0, st, partial,
+                       splits, n, frc, mu0, vel);
+    return hipGetLastError();
+}
+
+}  // namespace sd

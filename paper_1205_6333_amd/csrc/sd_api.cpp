@@ -1,0 +1,551 @@
+// sd_api.cpp -- the C ABI declared in include/sd.h: argument checks, library
+// workspace, launch configuration and the host side of the time loop.
+#include "sd.h"
+#include "sd_internal.h"
+#include "sd_host.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+namespace sd {
+
+// ------------------------------------------------------------------ errors
+
+static thread_local std::string g_last_error;
+
+sd_status fail(sd_status st, const char* fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return st;
+}
+
+sd_status ok()
+{
+    return SD_OK;
+}
+
+sd_status check_params(const sd_params* p)
+{
+    if (!p) return fail(SD_EINVAL, "params is NULL");
+    if (!(p->a > 0.0) || !std::isfinite(p->a)) return fail(SD_EINVAL, "a must be finite and > 0");
+    if (!(p->eta > 0.0) || !std::isfinite(p->eta))
+        return fail(SD_EINVAL, "eta must be finite and > 0");
+    if (p->tensor != SD_RPY && p->tensor != SD_OSEEN) return fail(SD_EINVAL, "unknown tensor");
+    if (p->overlap != SD_OVERLAP_NONE && p->overlap != SD_OVERLAP_RPY)
+        return fail(SD_EINVAL, "unknown overlap mode");
+    return SD_OK;
+}
+
+sd_status check_n(int64_t n)
+{
+    if (n < 1) return fail(SD_EINVAL, "n must be >= 1 (got %lld)", (long long)n);
+    if (n > MAX_N) return fail(SD_EINVAL, "n must be <= %lld (got %lld)", (long long)MAX_N,
+                               (long long)n);
+    return SD_OK;
+}
+
+sd_status check_precision(int32_t prec)
+{
+    if (prec != SD_FP32_KAHAN && prec != SD_FP64 && prec != SD_FP32_PLAIN)
+        return fail(SD_EINVAL, "unknown precision %d", prec);
+    return SD_OK;
+}
+
+sd_status check_ptr(const void* ptr, size_t align, const char* name)
+{
+    if (!ptr) return fail(SD_EINVAL, "%s is NULL", name);
+    if ((uintptr_t)ptr % align) return fail(SD_EALIGN, "%s is not %zu-byte aligned", name, align);
+    return SD_OK;
+}
+
+size_t vec4_align(int32_t prec)
+{
+    return prec == SD_FP64 ? 32 : 16;
+}
+
+// --------------------------------------------------------------- device info
+
+static std::mutex g_mu;
+
+struct DeviceInfo {
+    int cus = 0;
+};
+static std::map<int, DeviceInfo> g_dev;
+
+int device_cus()
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 256;
+    std::lock_guard<std::mutex> lk(g_mu);
+    auto& d = g_dev[dev];
+    if (d.cus == 0) {
+        hipDeviceProp_t prop;
+        if (hipGetDeviceProperties(&prop, dev) == hipSuccess && prop.multiProcessorCount > 0)
+            d.cus = prop.multiProcessorCount;
+        else
+            d.cus = 256;
+    }
+    return d.cus;
+}
+
+// ---------------------------------------------------------------- workspace
+
+struct Buffer {
+    void* ptr = nullptr;
+    size_t bytes = 0;
+};
+
+struct Workspace {
+    Buffer slot[WS_COUNT];
+};
+static std::map<int, Workspace> g_ws;
+
+// Returns a device buffer of at least `bytes` for workspace slot `which` on the
+// current device (grow-only; growing waits for the device to go idle).
+sd_status ws_get(int which, size_t bytes, void** out)
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return fail(SD_EDEVICE, "hipGetDevice failed");
+    std::lock_guard<std::mutex> lk(g_mu);
+    Buffer& b = g_ws[dev].slot[which];
+    if (b.bytes < bytes) {
+        if (b.ptr) {
+            (void)hipDeviceSynchronize();
+            (void)hipFree(b.ptr);
+            b.ptr = nullptr;
+            b.bytes = 0;
+        }
+        size_t want = std::max(bytes, (size_t)4096);
+        want = (want + 4095) & ~(size_t)4095;
+        if (hipMalloc(&b.ptr, want) != hipSuccess) {
+            (void)hipGetLastError();
+            b.ptr = nullptr;
+            return fail(SD_ENOMEM, "workspace allocation of %zu bytes failed", want);
+        }
+        b.bytes = want;
+    }
+    *out = b.ptr;
+    return SD_OK;
+}
+
+static sd_status ws_release_all()
+{
+    std::lock_guard<std::mutex> lk(g_mu);
+    int cur = 0;
+    (void)hipGetDevice(&cur);
+    for (auto& kv : g_ws) {
+        if (hipSetDevice(kv.first) != hipSuccess) continue;
+        (void)hipDeviceSynchronize();
+        for (auto& b : kv.second.slot)
+            if (b.ptr) {
+                (void)hipFree(b.ptr);
+                b.ptr = nullptr;
+                b.bytes = 0;
+            }
+    }
+    (void)hipSetDevice(cur);
+    return SD_OK;
+}
+
+// ------------------------------------------------------------ configuration
+
+struct ConfigTable {
+    bool forced = false;
+    sd_kernel_config forced_cfg{};
+    // tuned entries by size class (floor(log2 n))
+    std::map<int, sd_kernel_config> tuned;
+};
+static ConfigTable g_cfg[3];
+
+static int size_class(int64_t n)
+{
+    int c = 0;
+    while ((int64_t(1) << (c + 1)) <= n) ++c;
+    return c;
+}
+
+sd_kernel_config default_config(int32_t prec, int64_t n)
+{
+    sd_kernel_config c;
+    c.variant = 0;
+    c.block = 256;
+    c.ilp = 1;
+    c.kahan_block = (prec == SD_FP32_PLAIN) ? 0 : 4;
+    if (prec == SD_FP64) {
+        c.variant = 0;
+        c.kahan_block = 0;
+    }
+    // enough work-groups for two rounds of 4 resident waves per SIMD
+    const int cus = device_cus();
+    const int64_t iblocks = (n + c.block * c.ilp - 1) / (c.block * c.ilp);
+    const int64_t target = (int64_t)cus * (16 / (c.block / 64)) * 2;
+    int64_t s = std::max<int64_t>(1, (target + iblocks - 1) / iblocks);
+    const int64_t tiles = (n + c.block - 1) / c.block;
+    s = std::min<int64_t>(s, tiles);
+    s = std::min<int64_t>(s, 256);
+    c.splits = (int32_t)s;
+    return c;
+}
+
+sd_kernel_config choose_config(int32_t prec, int64_t n)
+{
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        const ConfigTable& t = g_cfg[prec];
+        if (t.forced) return t.forced_cfg;
+        auto it = t.tuned.find(size_class(n));
+        if (it != t.tuned.end()) {
+            sd_kernel_config c = it->second;
+            // keep the split count proportional to the size class
+            const int64_t tiles = (n + c.block - 1) / c.block;
+            if (c.splits > tiles) c.splits = (int32_t)tiles;
+            return c;
+        }
+    }
+    return default_config(prec, n);
+}
+
+void set_tuned_config(int32_t prec, int64_t n, const sd_kernel_config& c)
+{
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_cfg[prec].tuned[size_class(n)] = c;
+}
+
+sd_status check_config(int32_t prec, const sd_kernel_config& c)
+{
+    if (c.block != 64 && c.block != 128 && c.block != 256)
+        return fail(SD_EINVAL, "block must be 64, 128 or 256");
+    if (c.splits < 1) return fail(SD_EINVAL, "splits must be >= 1");
+    if (c.variant != 0 && c.variant != 1) return fail(SD_EINVAL, "variant must be 0 or 1");
+    if (c.ilp != 1 && c.ilp != 2) return fail(SD_EINVAL, "ilp must be 1 or 2");
+    if (prec == SD_FP64) {
+        if (c.variant != 0 || c.ilp != 1)
+            return fail(SD_EINVAL, "the FP64 path has variant 0 and ilp 1 only");
+    } else if (prec == SD_FP32_PLAIN) {
+        if (c.kahan_block != 0) return fail(SD_EINVAL, "kahan_block must be 0 for SD_FP32_PLAIN");
+    } else if (c.kahan_block != 1 && c.kahan_block != 2 && c.kahan_block != 4) {
+        return fail(SD_EINVAL, "kahan_block must be 1, 2 or 4 for SD_FP32_KAHAN");
+    }
+    return SD_OK;
+}
+
+// ---------------------------------------------------------------- profiling
+
+struct Profile {
+    bool on = false;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> pending;
+    int64_t launches = 0;
+    double total_ms = 0.0;
+};
+static Profile g_prof;
+
+static void prof_begin(hipStream_t st, hipEvent_t* a)
+{
+    *a = nullptr;
+    if (!g_prof.on) return;
+    if (hipEventCreate(a) != hipSuccess) {
+        *a = nullptr;
+        return;
+    }
+    (void)hipEventRecord(*a, st);
+}
+
+static void prof_end(hipStream_t st, hipEvent_t a)
+{
+    if (!a) return;
+    hipEvent_t b;
+    if (hipEventCreate(&b) != hipSuccess) {
+        (void)hipEventDestroy(a);
+        return;
+    }
+    (void)hipEventRecord(b, st);
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_prof.pending.emplace_back(a, b);
+}
+
+// ----------------------------------------------------------- product launch
+
+PairConst pair_const(const sd_params* p)
+{
+    return make_pair_const(p->a, p->eta, p->tensor, p->overlap);
+}
+
+// Launch the pair kernel for n particles; returns the number of splits used
+// through *splits_out.  partial is sized by the caller via partial_bytes().
+sd_status run_pair(const sd_params* p, int64_t n, const void* pos, const void* frc,
+                   const double* x64, int32_t prec, double* partial, const PairLaunch& L,
+                   hipStream_t st)
+{
+    const PairConst pc = pair_const(p);
+    hipEvent_t ev;
+    prof_begin(st, &ev);
+    hipError_t e;
+    if (prec == SD_FP64)
+        e = launch_pair_f64(L, p->tensor, (const double4*)pos, (const double4*)frc, (int)n, pc,
+                            partial, st);
+    else
+        e = launch_pair_f32(L, p->tensor, L.acc, (const float4*)pos, (const float4*)frc, x64,
+                            (int)n, pc, partial, st);
+    prof_end(st, ev);
+    if (e != hipSuccess) return fail(SD_EDEVICE, "pair kernel launch: %s", hipGetErrorString(e));
+    return SD_OK;
+}
+
+PairLaunch plan_pair(int32_t prec, int64_t n)
+{
+    const sd_kernel_config c = choose_config(prec, n);
+    PairLaunch L = shape_pair_launch((int)n, c.variant, c.block, c.splits, c.ilp);
+    L.acc = (prec == SD_FP64) ? 0 : c.kahan_block;
+    if (prec == SD_FP32_PLAIN) L.acc = 0;
+    return L;
+}
+
+size_t partial_bytes(const PairLaunch& L, int64_t n)
+{
+    return (size_t)L.splits * 3 * (size_t)n * sizeof(double);
+}
+
+}  // namespace sd
+
+using namespace sd;
+
+// ====================================================================== ABI
+
+extern "C" {
+
+sd_status mobility_apply(const sd_params* p, int64_t n, const void* pos, const void* force,
+                         double* vel, int32_t precision, void* stream)
+{
+    sd_status st;
+    if ((st = check_params(p)) || (st = check_n(n)) || (st = check_precision(precision))) return st;
+    const size_t al = vec4_align(precision);
+    if ((st = check_ptr(pos, al, "pos")) || (st = check_ptr(force, al, "force")) ||
+        (st = check_ptr(vel, 8, "vel")))
+        return st;
+    hipStream_t hs = (hipStream_t)stream;
+    const PairLaunch L = plan_pair(precision, n);
+    void* partial = nullptr;
+    if ((st = ws_get(WS_PARTIAL, partial_bytes(L, n), &partial))) return st;
+    if ((st = run_pair(p, n, pos, force, nullptr, precision, (double*)partial, L, hs))) return st;
+    hipError_t e = (precision == SD_FP64)
+                       ? launch_merge_f64((double*)partial, L.splits, (int)n, (const double4*)force,
+                                          1.0 / (6.0 * M_PI * p->eta * p->a), vel, hs)
+                       : launch_merge_f32((double*)partial, L.splits, (int)n, (const float4*)force,
+                                          1.0 / (6.0 * M_PI * p->eta * p->a), vel, hs);
+    if (e != hipSuccess) return fail(SD_EDEVICE, "merge kernel launch: %s", hipGetErrorString(e));
+    return SD_OK;
+}
+
+// One time step from x (FP64).  pos_stage holds the staged copy of x on entry
+// when `staged` is true.
+static sd_status step_impl(const sd_params* p, int64_t n, double* x, const void* force,
+                           double* v_prev, double* v_out, double dt, int64_t step_index,
+                           int32_t integrator, int32_t prec, void* pos_stage, bool staged,
+                           bool stage_next, double* partial, const PairLaunch& L, hipStream_t hs)
+{
+    sd_status st;
+    hipError_t e;
+    if (!staged) {
+        e = (prec == SD_FP64) ? launch_stage_f64(x, (double4*)pos_stage, (int)n, hs)
+                              : launch_stage_f32(x, (float4*)pos_stage, (int)n, hs);
+        if (e != hipSuccess) return fail(SD_EDEVICE, "stage launch: %s", hipGetErrorString(e));
+    }
+    if ((st = run_pair(p, n, pos_stage, force, prec == SD_FP64 ? nullptr : x, prec, partial, L,
+                       hs)))
+        return st;
+    const int mode = (integrator == SD_EULER) ? 0 : (step_index == 0 ? 1 : 2);
+    const double mu0 = 1.0 / (6.0 * M_PI * p->eta * p->a);
+    if (prec == SD_FP64)
+        e = launch_merge_integrate_f64(partial, L.splits, (int)n, (const double4*)force, mu0, x,
+                                       v_prev, v_out, dt, mode,
+                                       stage_next ? (double4*)pos_stage : nullptr, hs);
+    else
+        e = launch_merge_integrate_f32(partial, L.splits, (int)n, (const float4*)force, mu0, x,
+                                       v_prev, v_out, dt, mode,
+                                       stage_next ? (float4*)pos_stage : nullptr, hs);
+    if (e != hipSuccess) return fail(SD_EDEVICE, "integrate launch: %s", hipGetErrorString(e));
+    return SD_OK;
+}
+
+static sd_status check_step_args(const sd_params* p, int64_t n, const double* x, const void* force,
+                                 const double* v_prev, double dt, int32_t integrator,
+                                 int32_t precision)
+{
+    sd_status st;
+    if ((st = check_params(p)) || (st = check_n(n)) || (st = check_precision(precision))) return st;
+    if ((st = check_ptr(x, 8, "x")) || (st = check_ptr(force, vec4_align(precision), "force")))
+        return st;
+    if (!(dt > 0.0) || !std::isfinite(dt)) return fail(SD_EINVAL, "dt must be finite and > 0");
+    if (integrator != SD_EULER && integrator != SD_AB2) return fail(SD_EINVAL, "unknown integrator");
+    if (integrator == SD_AB2 && (st = check_ptr(v_prev, 8, "v_prev"))) return st;
+    if (v_prev && (uintptr_t)v_prev % 8) return fail(SD_EALIGN, "v_prev is not 8-byte aligned");
+    return SD_OK;
+}
+
+sd_status sd_step(const sd_params* p, int64_t n, double* x, const void* force, double* v_prev,
+                  double* v_out, double dt, int64_t step_index, int32_t integrator,
+                  int32_t precision, void* stream)
+{
+    sd_status st;
+    if ((st = check_step_args(p, n, x, force, v_prev, dt, integrator, precision))) return st;
+    if (step_index < 0) return fail(SD_EINVAL, "step_index must be >= 0");
+    if (v_out && (uintptr_t)v_out % 8) return fail(SD_EALIGN, "v_out is not 8-byte aligned");
+    hipStream_t hs = (hipStream_t)stream;
+    const PairLaunch L = plan_pair(precision, n);
+    void *partial = nullptr, *stage = nullptr;
+    if ((st = ws_get(WS_PARTIAL, partial_bytes(L, n), &partial)) ||
+        (st = ws_get(WS_STAGE, (size_t)n * (precision == SD_FP64 ? 32 : 16), &stage)))
+        return st;
+    return step_impl(p, n, x, force, integrator == SD_AB2 ? v_prev : nullptr, v_out, dt,
+                     step_index, integrator, precision, stage, false, false, (double*)partial, L,
+                     hs);
+}
+
+sd_status sd_run(const sd_params* p, int64_t n, double* x, const void* force, double* v_prev,
+                 double dt, int64_t steps, int64_t step0, int32_t integrator, int32_t precision,
+                 double* x_checkpoints, int64_t checkpoint_every, void* stream)
+{
+    sd_status st;
+    if ((st = check_step_args(p, n, x, force, v_prev, dt, integrator, precision))) return st;
+    if (steps < 0 || step0 < 0) return fail(SD_EINVAL, "steps and step0 must be >= 0");
+    if (x_checkpoints) {
+        if ((uintptr_t)x_checkpoints % 8) return fail(SD_EALIGN, "x_checkpoints misaligned");
+        if (checkpoint_every < 1) return fail(SD_EINVAL, "checkpoint_every must be >= 1");
+    }
+    hipStream_t hs = (hipStream_t)stream;
+    const size_t frame = 3 * (size_t)n * sizeof(double);
+    if (x_checkpoints && hipMemcpyAsync(x_checkpoints, x, frame, hipMemcpyDeviceToDevice, hs) !=
+                             hipSuccess)
+        return fail(SD_EDEVICE, "checkpoint copy failed");
+    if (steps == 0) return SD_OK;
+    const PairLaunch L = plan_pair(precision, n);
+    void *partial = nullptr, *stage = nullptr;
+    if ((st = ws_get(WS_PARTIAL, partial_bytes(L, n), &partial)) ||
+        (st = ws_get(WS_STAGE, (size_t)n * (precision == SD_FP64 ? 32 : 16), &stage)))
+        return st;
+    double* vp = integrator == SD_AB2 ? v_prev : nullptr;
+    for (int64_t s = 0; s < steps; ++s) {
+        if ((st = step_impl(p, n, x, force, vp, nullptr, dt, step0 + s, integrator, precision, stage,
+                            s > 0, s + 1 < steps, (double*)partial, L, hs)))
+            return st;
+        if (x_checkpoints && (s + 1) % checkpoint_every == 0) {
+            double* dst = x_checkpoints + 3 * (size_t)n * (size_t)((s + 1) / checkpoint_every);
+            if (hipMemcpyAsync(dst, x, frame, hipMemcpyDeviceToDevice, hs) != hipSuccess)
+                return fail(SD_EDEVICE, "checkpoint copy failed");
+        }
+    }
+    return SD_OK;
+}
+
+sd_status sd_set_kernel_config(int32_t precision, const sd_kernel_config* cfg)
+{
+    sd_status st;
+    if ((st = check_precision(precision))) return st;
+    if (cfg && (st = check_config(precision, *cfg))) return st;
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_cfg[precision].forced = cfg != nullptr;
+    if (cfg) g_cfg[precision].forced_cfg = *cfg;
+    return SD_OK;
+}
+
+sd_status sd_get_kernel_config(int32_t precision, int64_t n, sd_kernel_config* out)
+{
+    sd_status st;
+    if ((st = check_precision(precision)) || (st = check_n(n))) return st;
+    if (!out) return fail(SD_EINVAL, "out is NULL");
+    *out = choose_config(precision, n);
+    return SD_OK;
+}
+
+sd_status sd_profile_enable(int32_t on)
+{
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_prof.on = on != 0;
+    return SD_OK;
+}
+
+sd_status sd_profile_read(int64_t* launches, double* total_ms)
+{
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> pend;
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        pend.swap(g_prof.pending);
+    }
+    sd_status st = SD_OK;
+    int64_t cnt = 0;
+    double ms = 0.0;
+    for (auto& ab : pend) {
+        float t = 0.0f;
+        if (hipEventSynchronize(ab.second) != hipSuccess ||
+            hipEventElapsedTime(&t, ab.first, ab.second) != hipSuccess)
+            st = fail(SD_EDEVICE, "profiling event query failed");
+        else {
+            ms += t;
+            ++cnt;
+        }
+        (void)hipEventDestroy(ab.first);
+        (void)hipEventDestroy(ab.second);
+    }
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_prof.launches += cnt;
+    g_prof.total_ms += ms;
+    if (launches) *launches = g_prof.launches;
+    if (total_ms) *total_ms = g_prof.total_ms;
+    return st;
+}
+
+sd_status sd_profile_reset(void)
+{
+    int64_t l;
+    double t;
+    sd_profile_read(&l, &t);
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_prof.launches = 0;
+    g_prof.total_ms = 0.0;
+    return SD_OK;
+}
+
+sd_status sd_release(void)
+{
+    batch_release_graphs();
+    return ws_release_all();
+}
+
+const char* sd_status_string(int32_t s)
+{
+    switch (s) {
+    case SD_OK: return "SD_OK";
+    case SD_EINVAL: return "SD_EINVAL: invalid argument";
+    case SD_EALIGN: return "SD_EALIGN: misaligned pointer";
+    case SD_ENOMEM: return "SD_ENOMEM: out of device memory";
+    case SD_EDEVICE: return "SD_EDEVICE: HIP runtime or launch error";
+    case SD_EUNSUPPORTED: return "SD_EUNSUPPORTED: not implemented for these arguments";
+    default: return "unknown sd_status";
+    }
+}
+
+const char* sd_last_error(void)
+{
+    return g_last_error.c_str();
+}
+
+int32_t sd_version(void)
+{
+    return 100;
+}
+
+}  // extern "C"

@@ -1,0 +1,49 @@
+// sd_host.h -- host-side helpers shared by the C-ABI translation units
+// (argument checks, workspace, launch planning).  Not part of the C ABI.
+#pragma once
+
+#include "sd.h"
+#include "sd_internal.h"
+
+namespace sd {
+
+// Largest particle count the kernels index with 32-bit integers.
+constexpr int64_t MAX_N = (int64_t(1) << 30);
+
+// Library-owned workspace slots (one buffer each per device).
+enum {
+    WS_PARTIAL = 0,   // split partials of the pair kernels
+    WS_STAGE,         // FP32 / FP64 staged positions of the time loop
+    WS_ADJ_PARTIAL,   // split partials of the adjoint kernel
+    WS_ADJ_PACK,      // packed cotangent / force staging
+    WS_ADJ_TRAJ,      // recomputed trajectory of one checkpoint segment
+    WS_ADJ_LAM,       // adjoint state
+    WS_ADJ_CKPT,      // checkpoints when the caller passes none
+    WS_TUNE,          // autotuner scratch
+    WS_COUNT
+};
+
+sd_status fail(sd_status st, const char* fmt, ...);
+sd_status check_params(const sd_params* p);
+sd_status check_n(int64_t n);
+sd_status check_precision(int32_t prec);
+sd_status check_ptr(const void* ptr, size_t align, const char* name);
+size_t vec4_align(int32_t prec);
+int device_cus();
+sd_status ws_get(int which, size_t bytes, void** out);
+
+sd_kernel_config default_config(int32_t prec, int64_t n);
+sd_kernel_config choose_config(int32_t prec, int64_t n);
+void set_tuned_config(int32_t prec, int64_t n, const sd_kernel_config& c);
+sd_status check_config(int32_t prec, const sd_kernel_config& c);
+
+PairConst pair_const(const sd_params* p);
+PairLaunch plan_pair(int32_t prec, int64_t n);
+size_t partial_bytes(const PairLaunch& L, int64_t n);
+sd_status run_pair(const sd_params* p, int64_t n, const void* pos, const void* frc,
+                   const double* x64, int32_t prec, double* partial, const PairLaunch& L,
+                   hipStream_t st);
+
+void batch_release_graphs();
+
+}  // namespace sd

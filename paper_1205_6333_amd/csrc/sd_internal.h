@@ -1,0 +1,113 @@
+// sd_internal.h -- declarations shared by the HIP translation units of the
+// library (kernel launchers, constants, workspace).  Not part of the C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace sd {
+
+enum { T_RPY = 0, T_OSEEN = 1 };
+
+// Pair-tensor constants in the form the kernels use.
+//
+// Both tensors are written as T(r) = alpha [A'(r) I + Bt'(r) r r] with
+// alpha = 1/(8 pi eta) (= mu0 * 3a/4):
+//   Rotne-Prager, Eq. (7b):  A' = 1/r + gamma/r^3,  Bt' = (1 - 3 gamma/r^2)/r^3,
+//                            gamma = 2a^2/3
+//   Oseen, Eq. (4):          A' = 1/r,             Bt' = 1/r^3
+// so the FP32 fast path accumulates A' F + Bt' (d.F) d and the product with
+// alpha is taken once per particle, in FP64.  Pairs with r^2 < thr2 (near
+// contact, overlap, coincidence, self) skip the fast path and are evaluated in
+// FP64 from the same definitions.
+struct PairConst {
+    float gamma_f;       // 2a^2/3 (RPY) or 0 (Oseen)
+    float m3gamma_f;     // -3 gamma
+    float thr2_f;        // near threshold on r^2, FP32
+    int overlap;         // 1: overlap form for r < 2a (RPY only)
+    double thr2_d;       // near threshold on r^2, FP64
+    double alpha;        // 1/(8 pi eta)
+    double gamma;        // 2a^2/3 (RPY) or 0 (Oseen)
+    double mu0;          // 1/(6 pi eta a)
+    double a;
+};
+
+// Relative widening of the near threshold: pairs with r^2 < (2a)^2 (1 + NEAR_EPS)
+// are evaluated in FP64.
+constexpr double NEAR_EPS = 1e-3;
+
+PairConst make_pair_const(double a, double eta, int tensor, int overlap);
+
+struct PairLaunch {
+    int variant;   // 0 LDS tiles, 1 scalar-cache j stream
+    int block;     // threads per work-group
+    int splits;    // number of j-range splits actually launched
+    int jchunk;    // particles j per split (multiple of block)
+    int ilp;       // i per lane
+    int acc;       // FP32 accumulation: 0 plain, k = Kahan per k terms
+};
+
+// Shape the launch for n particles from a requested configuration.
+PairLaunch shape_pair_launch(int n, int variant, int block, int splits, int ilp);
+
+// Pair kernels: partial[(s*3 + k)*n + i] = sum over split s of the pair terms
+// (self excluded), FP64 output.
+// x64 (f64[3n], may be null): FP64 positions used for near pairs.
+hipError_t launch_pair_f32(const PairLaunch& L, int tensor, int acc, const float4* pos,
+                           const float4* frc, const double* x64, int n, const PairConst& pc,
+                           double* partial, hipStream_t st);
+hipError_t launch_pair_f64(const PairLaunch& L, int tensor, const double4* pos, const double4* frc,
+                           int n, const PairConst& pc, double* partial, hipStream_t st);
+
+// v_i = mu0 F_i + sum_s partial_s (fixed order).
+hipError_t launch_merge_f32(const double* partial, int splits, int n, const float4* frc, double mu0,
+                            double* vel, hipStream_t st);
+hipError_t launch_merge_f64(const double* partial, int splits, int n, const double4* frc,
+                            double mu0, double* vel, hipStream_t st);
+
+// Time loop helpers.
+hipError_t launch_stage_f32(const double* x, float4* pos, int n, hipStream_t st);
+hipError_t launch_stage_f64(const double* x, double4* pos, int n, hipStream_t st);
+// mode: 0 Euler, 1 AB2 start (Euler + store v_prev), 2 AB2
+hipError_t launch_merge_integrate_f32(const double* partial, int splits, int n, const float4* frc,
+                                      double mu0, double* x, double* v_prev, double* v_out,
+                                      double dt, int mode, float4* pos_next, hipStream_t st);
+hipError_t launch_merge_integrate_f64(const double* partial, int splits, int n, const double4* frc,
+                                      double mu0, double* x, double* v_prev, double* v_out,
+                                      double dt, int mode, double4* pos_next, hipStream_t st);
+
+// Adjoint pair kernels: partial[(s*3+k)*n + i] = position gradient terms.
+hipError_t launch_adjoint_f32(const PairLaunch& L, int tensor, const float4* pos, const float4* frc,
+                              const float4* lam, const double* x64, int n, const PairConst& pc,
+                              double* partial, hipStream_t st);
+hipError_t launch_adjoint_f64(const PairLaunch& L, int tensor, const double4* pos,
+                              const double4* frc, const double4* lam, int n, const PairConst& pc,
+                              double* partial, hipStream_t st);
+// out[3i+k] = sum_s partial (no self term); accumulate != 0 adds scale*sum to out.
+hipError_t launch_sum_partials(const double* partial, int splits, int n, double* out, double scale,
+                               int accumulate, hipStream_t st);
+// f64[3n] -> f32x4 / f64x4 (w = 0)
+hipError_t launch_pack_f32(const double* v, float4* out, int n, hipStream_t st);
+hipError_t launch_pack_f64(const double* v, double4* out, int n, hipStream_t st);
+// y[k] += s * x[k], k < m
+hipError_t launch_axpy(double s, const double* x, double* y, int64_t m, hipStream_t st);
+
+// Batched clusters.
+struct BatchDev {
+    const int64_t* offsets;   // device, C+1
+    const int32_t* order;     // device, C: processing order (longest first)
+    int32_t* counter;         // device, 1: work-queue head
+    int n_clusters;
+    int max_size;
+};
+hipError_t launch_batched_run(const BatchDev& b, int tensor, int precision, const PairConst& pc,
+                              double* x, const void* frc, double dt, int steps, int integrator,
+                              int n_workgroups, hipStream_t st);
+hipError_t launch_batched_apply(const BatchDev& b, int tensor, int precision, const PairConst& pc,
+                                const void* pos, const void* frc, double* vel, int n_workgroups,
+                                hipStream_t st);
+hipError_t launch_fill_i32(int32_t* p, int32_t value, int count, hipStream_t st);
+size_t batched_lds_bytes(int max_size, int precision, int integrator);
+
+}  // namespace sd

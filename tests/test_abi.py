@@ -1,0 +1,116 @@
+"""CPU checks of the C ABI: the library loads, exports every function the
+header declares, and rejects bad arguments before touching any device."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "sd.h")
+
+
+def _declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?[A-Za-z_][A-Za-z0-9_]*\s*\**\s+([a-z_][a-z0-9_]*)\s*\(",
+                       src, flags=re.M)
+    return sorted(set(names))
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_1205_6333_amd import binding
+    if not os.path.exists(binding.LIB_PATH):
+        from paper_1205_6333_amd import build
+        build.build()
+    return binding.lib()
+
+
+def test_header_declares_the_entry_points():
+    names = _declared_functions()
+    for must in ("mobility_apply", "mobility_adjoint", "sd_step", "sd_run", "sd_run_adjoint",
+                 "mobility_apply_batched", "sd_run_batched", "sd_batch_create", "sd_autotune",
+                 "sd_release", "sd_status_string"):
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol(L):
+    for name in _declared_functions():
+        assert hasattr(L, name), name
+
+
+def test_status_strings_and_version(L):
+    for s in range(6):
+        assert L.sd_status_string(s)
+    assert b"unknown" in L.sd_status_string(99)
+    assert L.sd_version() >= 100
+
+
+def test_argument_errors_before_device_work(L):
+    from paper_1205_6333_amd import binding as b
+    p = b.params()
+    vp = ctypes.c_void_p
+    ok16, bad = vp(1 << 20), vp((1 << 20) + 8)
+    # n < 1, NULL pointers, misalignment
+    assert L.mobility_apply(ctypes.byref(p), 0, ok16, ok16, ok16, 0, None) == b.SD_EINVAL
+    assert L.mobility_apply(ctypes.byref(p), 5, None, ok16, ok16, 0, None) == b.SD_EINVAL
+    assert L.mobility_apply(ctypes.byref(p), 5, bad, ok16, ok16, 0, None) == b.SD_EALIGN
+    assert L.mobility_apply(ctypes.byref(p), 5, vp((1 << 20) + 16), ok16, ok16, 1,
+                            None) == b.SD_EALIGN  # FP64 needs 32-byte records
+    assert L.mobility_apply(ctypes.byref(p), 5, ok16, ok16, vp((1 << 20) + 4), 0,
+                            None) == b.SD_EALIGN
+    # parameters and enums
+    for bad_p in (b.params(a=0.0), b.params(a=-1.0), b.params(eta=0.0), b.params(a=float("nan")),
+                  b.SdParams(1.0, 1.0, 7, 0), b.SdParams(1.0, 1.0, 0, 3)):
+        assert L.mobility_apply(ctypes.byref(bad_p), 5, ok16, ok16, ok16, 0, None) == b.SD_EINVAL
+    assert L.mobility_apply(None, 5, ok16, ok16, ok16, 0, None) == b.SD_EINVAL
+    assert L.mobility_apply(ctypes.byref(p), 5, ok16, ok16, ok16, 9, None) == b.SD_EINVAL
+    assert L.mobility_apply(ctypes.byref(p), 1 << 40, ok16, ok16, ok16, 0, None) == b.SD_EINVAL
+    # time loop
+    assert L.sd_step(ctypes.byref(p), 5, ok16, ok16, None, None, 0.0, 0, 0, 0, None) == b.SD_EINVAL
+    assert L.sd_step(ctypes.byref(p), 5, ok16, ok16, None, None, 0.1, -1, 0, 0, None) == b.SD_EINVAL
+    assert L.sd_step(ctypes.byref(p), 5, ok16, ok16, None, None, 0.1, 0, 1, 0, None) == b.SD_EINVAL
+    assert L.sd_step(ctypes.byref(p), 5, ok16, ok16, None, None, 0.1, 0, 4, 0, None) == b.SD_EINVAL
+    assert L.sd_run(ctypes.byref(p), 5, ok16, ok16, None, 0.1, -2, 0, 0, 0, None, 0,
+                    None) == b.SD_EINVAL
+    assert L.sd_run(ctypes.byref(p), 5, ok16, ok16, None, 0.1, 3, 0, 0, 0, ok16, 0,
+                    None) == b.SD_EINVAL
+    assert L.sd_run_adjoint(ctypes.byref(p), 5, ok16, ok16, 0.1, 3, 0, None, 0, ok16, ok16, ok16,
+                            None) == b.SD_EINVAL
+    assert L.mobility_adjoint(ctypes.byref(p), 5, ok16, ok16, None, ok16, ok16, 0,
+                              None) == b.SD_EINVAL
+    assert L.sd_last_error()
+
+
+def test_kernel_config_validation(L):
+    from paper_1205_6333_amd import binding as b
+    bad = [dict(variant=2, block=256, splits=1, ilp=1, kahan_block=4),
+           dict(variant=0, block=96, splits=1, ilp=1, kahan_block=4),
+           dict(variant=0, block=256, splits=0, ilp=1, kahan_block=4),
+           dict(variant=0, block=256, splits=1, ilp=3, kahan_block=4),
+           dict(variant=0, block=256, splits=1, ilp=1, kahan_block=3)]
+    for cfg in bad:
+        with pytest.raises(b.SdError):
+            b.sd_set_kernel_config(b.SD_FP32_KAHAN, cfg)
+    with pytest.raises(b.SdError):
+        b.sd_set_kernel_config(b.SD_FP64, dict(variant=1, block=256, splits=1, ilp=1,
+                                               kahan_block=0))
+    with pytest.raises(b.SdError):
+        b.sd_set_kernel_config(b.SD_FP32_PLAIN, dict(variant=0, block=256, splits=1, ilp=1,
+                                                     kahan_block=4))
+    b.sd_set_kernel_config(b.SD_FP32_KAHAN, None)
+
+
+def test_batch_plan_errors(L):
+    from paper_1205_6333_amd import binding as b
+    p = b.params()
+    h = ctypes.c_void_p()
+    offs = (ctypes.c_int64 * 3)(0, 5, 3)  # decreasing
+    assert L.sd_batch_create(ctypes.byref(p), 2, offs, ctypes.byref(h)) == b.SD_EINVAL
+    offs = (ctypes.c_int64 * 3)(1, 5, 9)  # does not start at 0
+    assert L.sd_batch_create(ctypes.byref(p), 2, offs, ctypes.byref(h)) == b.SD_EINVAL
+    offs = (ctypes.c_int64 * 2)(0, 5000)  # cluster above the maximum size
+    assert L.sd_batch_create(ctypes.byref(p), 1, offs, ctypes.byref(h)) == b.SD_EINVAL
+    assert L.sd_batch_create(ctypes.byref(p), 0, offs, ctypes.byref(h)) == b.SD_EINVAL
+    assert L.sd_batch_create(ctypes.byref(p), 1, None, ctypes.byref(h)) == b.SD_EINVAL
