@@ -242,6 +242,14 @@ sd_status sd_profile_reset(void);
 
 /* --------------------------------------------------------------------- misc */
 
+/*
+ * sd_pack -- stage vectors for the product entry points: f64[3n] -> f32x4[n]
+ * (FP32 precisions, values rounded to nearest) or f64x4[n] (SD_FP64), w = 0.
+ * This is the FP64 -> FP32 staging step the time loop applies to positions
+ * before every product.
+ */
+sd_status sd_pack(int64_t n, const double* v, void* out, int32_t precision, void* stream);
+
 /* Frees library-owned device workspace on every device (staging copies,
  * split partials).  Safe to call at any time when no library work is pending. */
 sd_status sd_release(void);

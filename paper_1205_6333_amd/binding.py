@@ -74,6 +74,7 @@ def lib() -> ctypes.CDLL:
             "sd_set_kernel_config": [i32, ctypes.POINTER(SdKernelConfig)],
             "sd_get_kernel_config": [i32, i64, ctypes.POINTER(SdKernelConfig)],
             "sd_autotune": [P, i64, i32, vp, ctypes.c_char_p, i64],
+            "sd_pack": [i64, dp, vp, i32, vp],
             "sd_profile_enable": [i32],
             "sd_profile_read": [ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double)],
             "sd_profile_reset": [],
@@ -295,6 +296,21 @@ def sd_run_batched(batch: Batch, x, force, dt: float, steps: int, *, integrator:
     check(lib().sd_run_batched(batch._h, _ptr(x), _ptr(force), float(dt), int(steps),
                                int(integrator), prec, int(bool(use_graph)), _stream(stream)))
     return x
+
+
+def sd_pack(v, precision: int = SD_FP32_KAHAN, out=None, stream=None):
+    """(n, 3) float64 CUDA tensor -> (n, 4) float32 (FP32 precisions) or
+    float64 (SD_FP64) record tensor with w = 0, staged by the library's kernel."""
+    import torch
+    n = v.shape[0]
+    _vec3(v, n, "v")
+    prec = int(precision)
+    if out is None:
+        out = torch.empty((n, 4), dtype=torch.float64 if prec == SD_FP64 else torch.float32,
+                          device=v.device)
+    _vec4(out, prec, "out")
+    check(lib().sd_pack(n, _ptr(v), _ptr(out), prec, _stream(stream)))
+    return out
 
 
 def sd_set_kernel_config(precision: int, cfg: Optional[dict]) -> None:

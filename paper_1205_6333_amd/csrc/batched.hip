@@ -1,0 +1,631 @@
+// batched.hip -- many independent clusters, each a free-space suspension of
+// its own (the mobility product of Eq. 7a restricted to a cluster, advanced by
+// the step loop of Sec. 3.1), in ONE persistent kernel launch.
+//
+// Each 256-lane work-group pulls cluster ids from a device work queue (an
+// atomic counter over a longest-first order prepared on the host), loads the
+// cluster into LDS (FP64 master positions, forces, FP32 staged positions) and
+// runs all time steps without leaving the kernel: clusters never interact, so
+// no grid-wide synchronisation is needed.  Clusters of nc <= 256 particles get
+// P = 256 / nc lanes per particle, each summing every P-th j; the P partial
+// velocities are combined in LDS in a fixed order.  Larger clusters (up to
+// SD_BATCH_MAX_CLUSTER) give each lane ceil(nc / 256) particles.
+#include "sd.h"
+#include "sd_host.h"
+#include "sd_internal.h"
+
+#include <algorithm>
+#include <cmath>
+#include <numeric>
+#include <vector>
+
+namespace sd {
+
+constexpr int BB = 256;                          // lanes per work-group
+constexpr int MAX_ROWS = SD_BATCH_MAX_CLUSTER / BB;
+
+// LDS layout of one work-group (every segment 32-byte aligned):
+//   xs  f64[3M]   FP64 positions of the cluster
+//   fs  f32x4[M] or f64x4[M]   forces
+//   pf  f32x4[M]  FP32 staged positions (FP32 precisions)
+//   vp  f64[3M]   previous velocities (AB2)
+//   red f64[3*BB] per-lane partial velocities
+struct LdsLayout {
+    size_t fs, pf, vp, red, total;
+};
+
+__host__ __device__ inline size_t lds_round(size_t b) { return (b + 31) & ~(size_t)31; }
+
+__host__ __device__ inline LdsLayout lds_layout(int max_size, int precision, int integrator)
+{
+    const size_t M = (size_t)max_size;
+    LdsLayout L;
+    size_t o = lds_round(M * 3 * sizeof(double));
+    L.fs = o;
+    o += lds_round(M * (precision == SD_FP64 ? sizeof(double4) : sizeof(float4)));
+    L.pf = o;
+    if (precision != SD_FP64) o += lds_round(M * sizeof(float4));
+    L.vp = o;
+    if (integrator == SD_AB2) o += lds_round(M * 3 * sizeof(double));
+    L.red = o;
+    o += lds_round((size_t)BB * 3 * sizeof(double));
+    L.total = o;
+    return L;
+}
+
+size_t batched_lds_bytes(int max_size, int precision, int integrator)
+{
+    return lds_layout(max_size, precision, integrator).total;
+}
+
+// FP64 near-pair contribution (same definitions as the product kernels).
+template <int TENSOR>
+__device__ __forceinline__ void b_near(const PairConst& pc, double d0, double d1, double d2,
+                                       double f0, double f1, double f2, double* nv)
+{
+    const double r2 = d0 * d0 + d1 * d1 + d2 * d2;
+    if (r2 == 0.0) {
+        if (TENSOR == T_RPY && pc.overlap) {
+            nv[0] += pc.mu0 * f0;
+            nv[1] += pc.mu0 * f1;
+            nv[2] += pc.mu0 * f2;
+        }
+        return;
+    }
+    const double r = sqrt(r2);
+    double cI, cD;
+    if (TENSOR == T_OSEEN) {
+        cI = pc.alpha / r;
+        cD = cI / r2;
+    } else if (pc.overlap && r < 2.0 * pc.a) {
+        cI = pc.mu0 * (1.0 - 9.0 * r / (32.0 * pc.a));
+        cD = pc.mu0 * 3.0 / (32.0 * pc.a * r);
+    } else {
+        const double ri = 1.0 / r, ri2 = ri * ri, ri3 = ri * ri2;
+        cI = pc.alpha * (ri + pc.gamma * ri3);
+        cD = pc.alpha * ri3 * (1.0 - 3.0 * pc.gamma * ri2);
+    }
+    const double dF = d0 * f0 + d1 * f1 + d2 * f2;
+    nv[0] += cI * f0 + cD * dF * d0;
+    nv[1] += cI * f1 + cD * dF * d1;
+    nv[2] += cI * f2 + cD * dF * d2;
+}
+
+// Velocity (pair part, physical units, self term excluded) of particle i from
+// the j = sub, sub + P, ... of the cluster held in LDS.
+// PREC: 0 FP32 + Kahan (per term), 2 FP32 plain, 1 FP64.
+template <int TENSOR, int PREC>
+__device__ __forceinline__ void b_velocity(int i, int sub, int P, int nc, const double* xs,
+                                           const void* fsv, const float4* pf, const PairConst& pc,
+                                           double* v)
+{
+    double nv[3] = { 0.0, 0.0, 0.0 };
+    if (PREC == SD_FP64) {
+        const double4* fs = (const double4*)fsv;
+        const double xi0 = xs[3 * i], xi1 = xs[3 * i + 1], xi2 = xs[3 * i + 2];
+        double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+        for (int j = sub; j < nc; j += P) {
+            const double dx = xi0 - xs[3 * j], dy = xi1 - xs[3 * j + 1], dz = xi2 - xs[3 * j + 2];
+            const double4 fj = fs[j];
+            const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
+            if (r2 < pc.thr2_d) {
+                if (j != i) b_near<TENSOR>(pc, dx, dy, dz, fj.x, fj.y, fj.z, nv);
+                continue;
+            }
+            const double rinv = rsqrt(r2);
+            const double rinv2 = rinv * rinv, rinv3 = rinv2 * rinv;
+            double A = rinv, Bt = rinv3;
+            if (TENSOR == T_RPY) {
+                A = fma(pc.gamma, rinv3, rinv);
+                Bt = rinv3 * fma(-3.0 * pc.gamma, rinv2, 1.0);
+            }
+            const double sB = Bt * fma(dx, fj.x, fma(dy, fj.y, dz * fj.z));
+            a0 = fma(A, fj.x, fma(sB, dx, a0));
+            a1 = fma(A, fj.y, fma(sB, dy, a1));
+            a2 = fma(A, fj.z, fma(sB, dz, a2));
+        }
+        v[0] = pc.alpha * a0 + nv[0];
+        v[1] = pc.alpha * a1 + nv[1];
+        v[2] = pc.alpha * a2 + nv[2];
+        return;
+    }
+    const float4* fs = (const float4*)fsv;
+    const float4 pi = pf[i];
+    const float gamma = pc.gamma_f, m3g = pc.m3gamma_f, thr2 = pc.thr2_f;
+    float s0 = 0.f, s1 = 0.f, s2 = 0.f, c0 = 0.f, c1 = 0.f, c2 = 0.f;
+    for (int j = sub; j < nc; j += P) {
+        const float4 pj = pf[j];
+        const float4 fj = fs[j];
+        const float dx = pi.x - pj.x, dy = pi.y - pj.y, dz = pi.z - pj.z;
+        const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+        if (r2 < thr2) {
+            if (j != i)
+                b_near<TENSOR>(pc, xs[3 * i] - xs[3 * j], xs[3 * i + 1] - xs[3 * j + 1],
+                               xs[3 * i + 2] - xs[3 * j + 2], fj.x, fj.y, fj.z, nv);
+            continue;
+        }
+        const float rinv = __builtin_amdgcn_rsqf(r2);
+        const float rinv2 = rinv * rinv, rinv3 = rinv2 * rinv;
+        float A = rinv, Bt = rinv3;
+        if (TENSOR == T_RPY) {
+            A = fmaf(gamma, rinv3, rinv);
+            Bt = rinv3 * fmaf(m3g, rinv2, 1.0f);
+        }
+        const float sB = Bt * fmaf(dx, fj.x, fmaf(dy, fj.y, dz * fj.z));
+        if (PREC == SD_FP32_KAHAN) {
+            const float y0 = fmaf(A, fj.x, fmaf(sB, dx, -c0));
+            const float y1 = fmaf(A, fj.y, fmaf(sB, dy, -c1));
+            const float y2 = fmaf(A, fj.z, fmaf(sB, dz, -c2));
+            const float t0 = s0 + y0, t1 = s1 + y1, t2 = s2 + y2;
+            c0 = (t0 - s0) - y0;
+            c1 = (t1 - s1) - y1;
+            c2 = (t2 - s2) - y2;
+            s0 = t0;
+            s1 = t1;
+            s2 = t2;
+        } else {
+            s0 = fmaf(A, fj.x, fmaf(sB, dx, s0));
+            s1 = fmaf(A, fj.y, fmaf(sB, dy, s1));
+            s2 = fmaf(A, fj.z, fmaf(sB, dz, s2));
+        }
+    }
+    v[0] = pc.alpha * ((double)s0 - (double)c0) + nv[0];
+    v[1] = pc.alpha * ((double)s1 - (double)c1) + nv[1];
+    v[2] = pc.alpha * ((double)s2 - (double)c2) + nv[2];
+}
+
+// RUN: `steps` steps per cluster, positions written back to x.
+// APPLY (steps < 0): one product, velocities written to vel.
+template <int TENSOR, int PREC, int INTEG>
+__global__ void __launch_bounds__(BB)
+k_batched(BatchDev b, PairConst pc, double* __restrict__ x, const void* __restrict__ frc,
+          double* __restrict__ vel, double dt, int steps)
+{
+    extern __shared__ __align__(32) unsigned char lds[];
+    const LdsLayout lay = lds_layout(b.max_size, PREC, INTEG);
+    double* xs = (double*)lds;
+    void* fs = lds + lay.fs;
+    float4* pf = (PREC != SD_FP64) ? (float4*)(lds + lay.pf) : nullptr;
+    double* vp = (INTEG == SD_AB2) ? (double*)(lds + lay.vp) : nullptr;
+    double* red = (double*)(lds + lay.red);
+    __shared__ int s_item;
+    const int t = threadIdx.x;
+
+    for (;;) {
+        __syncthreads();
+        if (t == 0) s_item = atomicAdd(b.counter, 1);
+        __syncthreads();
+        const int item = s_item;
+        if (item >= b.n_clusters) break;  // every work-group exits once the queue is empty
+        const int c = b.order[item];
+        const int64_t off = b.offsets[c];
+        const int nc = (int)(b.offsets[c + 1] - off);
+        if (nc <= 0) continue;
+        for (int k = t; k < nc; k += BB) {
+            const size_t g = (size_t)(off + k);
+            xs[3 * k] = x[3 * g];
+            xs[3 * k + 1] = x[3 * g + 1];
+            xs[3 * k + 2] = x[3 * g + 2];
+            if (PREC == SD_FP64)
+                ((double4*)fs)[k] = ((const double4*)frc)[g];
+            else
+                ((float4*)fs)[k] = ((const float4*)frc)[g];
+        }
+        const int P = nc <= BB ? BB / nc : 1;
+        const int rows = nc <= BB ? 1 : (nc + BB - 1) / BB;
+        const int nsteps = steps < 0 ? 1 : steps;
+        for (int st = 0; st < nsteps; ++st) {
+            __syncthreads();
+            if (PREC != SD_FP64)
+                for (int k = t; k < nc; k += BB)
+                    pf[k] = make_float4((float)xs[3 * k], (float)xs[3 * k + 1],
+                                        (float)xs[3 * k + 2], 0.0f);
+            __syncthreads();
+            double v[MAX_ROWS][3];
+            if (P > 1) {
+                const int i = t / P, sub = t % P;
+                double w[3] = { 0.0, 0.0, 0.0 };
+                if (i < nc) b_velocity<TENSOR, PREC>(i, sub, P, nc, xs, fs, pf, pc, w);
+                red[3 * t] = w[0];
+                red[3 * t + 1] = w[1];
+                red[3 * t + 2] = w[2];
+                __syncthreads();
+                v[0][0] = v[0][1] = v[0][2] = 0.0;
+                if (sub == 0 && i < nc)
+                    for (int u = 0; u < P; ++u) {
+                        v[0][0] += red[3 * (t + u)];
+                        v[0][1] += red[3 * (t + u) + 1];
+                        v[0][2] += red[3 * (t + u) + 2];
+                    }
+            } else {
+#pragma unroll
+                for (int r = 0; r < MAX_ROWS; ++r) {
+                    const int i = t + r * BB;
+                    v[r][0] = v[r][1] = v[r][2] = 0.0;
+                    if (r < rows && i < nc)
+                        b_velocity<TENSOR, PREC>(i, 0, 1, nc, xs, fs, pf, pc, v[r]);
+                }
+            }
+            __syncthreads();  // every read of xs / pf of this step is done
+            const int nrow = P > 1 ? 1 : rows;
+#pragma unroll
+            for (int r = 0; r < MAX_ROWS; ++r) {
+                if (r >= nrow) break;
+                const int i = (P > 1) ? t / P : t + r * BB;
+                const bool own = (P > 1) ? (t % P == 0 && i < nc) : (i < nc);
+                if (!own) continue;
+                double f0, f1, f2;
+                if (PREC == SD_FP64) {
+                    const double4 f = ((const double4*)fs)[i];
+                    f0 = f.x; f1 = f.y; f2 = f.z;
+                } else {
+                    const float4 f = ((const float4*)fs)[i];
+                    f0 = f.x; f1 = f.y; f2 = f.z;
+                }
+                const double vv[3] = { pc.mu0 * f0 + v[r][0], pc.mu0 * f1 + v[r][1],
+                                       pc.mu0 * f2 + v[r][2] };
+                if (steps < 0) {
+                    const size_t g = (size_t)(off + i);
+                    vel[3 * g] = vv[0];
+                    vel[3 * g + 1] = vv[1];
+                    vel[3 * g + 2] = vv[2];
+                    continue;
+                }
+                for (int k = 0; k < 3; ++k) {
+                    double inc = vv[k];
+                    if (INTEG == SD_AB2) {
+                        if (st > 0) inc = 1.5 * vv[k] - 0.5 * vp[3 * i + k];
+                        vp[3 * i + k] = vv[k];
+                    }
+                    xs[3 * i + k] += dt * inc;
+                }
+            }
+        }
+        if (steps >= 0) {
+            __syncthreads();
+            for (int k = t; k < nc; k += BB) {
+                const size_t g = (size_t)(off + k);
+                x[3 * g] = xs[3 * k];
+                x[3 * g + 1] = xs[3 * k + 1];
+                x[3 * g + 2] = xs[3 * k + 2];
+            }
+        }
+    }
+}
+
+template <int TENSOR, int PREC, int INTEG>
+static hipError_t launch_b(const BatchDev& b, const PairConst& pc, double* x, const void* frc,
+                           double* vel, double dt, int steps, int nwg, hipStream_t st)
+{
+    const size_t lds = batched_lds_bytes(b.max_size, PREC, INTEG);
+    if (lds > 64 * 1024) {
+        hipError_t e = hipFuncSetAttribute((const void*)k_batched<TENSOR, PREC, INTEG>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL((k_batched<TENSOR, PREC, INTEG>), dim3(nwg), dim3(BB), lds, st, b, pc, x,
+                       frc, vel, dt, steps);
+    return hipGetLastError();
+}
+
+template <int TENSOR>
+static hipError_t launch_bt(const BatchDev& b, int prec, int integ, const PairConst& pc, double* x,
+                            const void* frc, double* vel, double dt, int steps, int nwg,
+                            hipStream_t st)
+{
+    switch (prec * 2 + integ) {
+    case SD_FP32_KAHAN * 2 + SD_EULER:
+        return launch_b<TENSOR, SD_FP32_KAHAN, SD_EULER>(b, pc, x, frc, vel, dt, steps, nwg, st);
+    case SD_FP32_KAHAN * 2 + SD_AB2:
+        return launch_b<TENSOR, SD_FP32_KAHAN, SD_AB2>(b, pc, x, frc, vel, dt, steps, nwg, st);
+    case SD_FP64 * 2 + SD_EULER:
+        return launch_b<TENSOR, SD_FP64, SD_EULER>(b, pc, x, frc, vel, dt, steps, nwg, st);
+    case SD_FP64 * 2 + SD_AB2:
+        return launch_b<TENSOR, SD_FP64, SD_AB2>(b, pc, x, frc, vel, dt, steps, nwg, st);
+    case SD_FP32_PLAIN * 2 + SD_EULER:
+        return launch_b<TENSOR, SD_FP32_PLAIN, SD_EULER>(b, pc, x, frc, vel, dt, steps, nwg, st);
+    case SD_FP32_PLAIN * 2 + SD_AB2:
+        return launch_b<TENSOR, SD_FP32_PLAIN, SD_AB2>(b, pc, x, frc, vel, dt, steps, nwg, st);
+    }
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_batched_run(const BatchDev& b, int tensor, int precision, const PairConst& pc,
+                              double* x, const void* frc, double dt, int steps, int integrator,
+                              int n_workgroups, hipStream_t st)
+{
+    return tensor == T_OSEEN
+               ? launch_bt<T_OSEEN>(b, precision, integrator, pc, x, frc, nullptr, dt, steps,
+                                    n_workgroups, st)
+               : launch_bt<T_RPY>(b, precision, integrator, pc, x, frc, nullptr, dt, steps,
+                                  n_workgroups, st);
+}
+
+hipError_t launch_batched_apply(const BatchDev& b, int tensor, int precision, const PairConst& pc,
+                                const void* pos, const void* frc, double* vel, int n_workgroups,
+                                hipStream_t st)
+{
+    // APPLY reads positions as f64[3 total] (the caller stages them)
+    return tensor == T_OSEEN
+               ? launch_bt<T_OSEEN>(b, precision, SD_EULER, pc, (double*)pos, frc, vel, 0.0, -1,
+                                    n_workgroups, st)
+               : launch_bt<T_RPY>(b, precision, SD_EULER, pc, (double*)pos, frc, vel, 0.0, -1,
+                                  n_workgroups, st);
+}
+
+// f32x4 / f64x4 positions -> f64[3 n]
+__global__ void __launch_bounds__(256) k_unpack_f32(const float4* __restrict__ p,
+                                                   double* __restrict__ x, int n)
+{
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    const float4 v = p[i];
+    x[3 * (size_t)i] = v.x;
+    x[3 * (size_t)i + 1] = v.y;
+    x[3 * (size_t)i + 2] = v.z;
+}
+__global__ void __launch_bounds__(256) k_unpack_f64(const double4* __restrict__ p,
+                                                   double* __restrict__ x, int n)
+{
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    const double4 v = p[i];
+    x[3 * (size_t)i] = v.x;
+    x[3 * (size_t)i + 1] = v.y;
+    x[3 * (size_t)i + 2] = v.z;
+}
+
+// ---------------------------------------------------------------- the plan
+
+struct GraphKey {
+    double* x = nullptr;
+    const void* frc = nullptr;
+    double dt = 0.0;
+    int64_t steps = -1;
+    int32_t integ = -1, prec = -1, nwg = 0;
+    bool operator==(const GraphKey& o) const
+    {
+        return x == o.x && frc == o.frc && dt == o.dt && steps == o.steps && integ == o.integ &&
+               prec == o.prec && nwg == o.nwg;
+    }
+};
+
+}  // namespace sd
+
+struct sd_batch {
+    int dev = 0;
+    sd_params p{};
+    int64_t n_clusters = 0;
+    int64_t total = 0;
+    int max_size = 0;
+    void* dmem = nullptr;       // offsets | order | counter
+    int64_t* d_offsets = nullptr;
+    int32_t* d_order = nullptr;
+    int32_t* d_counter = nullptr;
+    hipStream_t cap = nullptr;  // private stream used only for graph capture
+    sd::GraphKey key;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+namespace sd {
+
+static std::vector<sd_batch*> g_batches;
+
+static void drop_graph(sd_batch* b)
+{
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    b->exec = nullptr;
+    b->graph = nullptr;
+    b->key = GraphKey();
+}
+
+void batch_release_graphs()
+{
+    for (sd_batch* b : g_batches) drop_graph(b);
+}
+
+static int batch_workgroups(const sd_batch* b, int prec, int integ)
+{
+    const int cus = device_cus();
+    const size_t lds = batched_lds_bytes(b->max_size, prec, integ);
+    int per_cu = (int)std::min<size_t>(4, (160 * 1024) / std::max<size_t>(lds, 1));
+    per_cu = std::max(per_cu, 1);
+    const int64_t want = (int64_t)cus * per_cu;
+    return (int)std::max<int64_t>(1, std::min<int64_t>(want, b->n_clusters));
+}
+
+static BatchDev batch_dev(const sd_batch* b)
+{
+    BatchDev d;
+    d.offsets = b->d_offsets;
+    d.order = b->d_order;
+    d.counter = b->d_counter;
+    d.n_clusters = (int)b->n_clusters;
+    d.max_size = std::max(1, b->max_size);
+    return d;
+}
+
+static sd_status check_batch(const sd_batch* b)
+{
+    if (!b) return fail(SD_EINVAL, "batch is NULL");
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return fail(SD_EDEVICE, "hipGetDevice failed");
+    if (dev != b->dev) return fail(SD_EINVAL, "batch plan belongs to device %d, current is %d",
+                                   b->dev, dev);
+    return SD_OK;
+}
+
+}  // namespace sd
+
+using namespace sd;
+
+extern "C" {
+
+sd_status sd_batch_create(const sd_params* p, int64_t n_clusters, const int64_t* offsets,
+                          sd_batch** out)
+{
+    sd_status st;
+    if ((st = check_params(p))) return st;
+    if (!out) return fail(SD_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (n_clusters < 1 || n_clusters > (int64_t(1) << 30))
+        return fail(SD_EINVAL, "n_clusters must be in [1, 2^30]");
+    if (!offsets) return fail(SD_EINVAL, "offsets is NULL");
+    if (offsets[0] != 0) return fail(SD_EINVAL, "offsets[0] must be 0");
+    int max_size = 0;
+    for (int64_t c = 0; c < n_clusters; ++c) {
+        const int64_t sz = offsets[c + 1] - offsets[c];
+        if (sz < 0) return fail(SD_EINVAL, "offsets must be non-decreasing (cluster %lld)",
+                                (long long)c);
+        if (sz > SD_BATCH_MAX_CLUSTER)
+            return fail(SD_EINVAL, "cluster %lld has %lld particles (max %d)", (long long)c,
+                        (long long)sz, SD_BATCH_MAX_CLUSTER);
+        max_size = std::max(max_size, (int)sz);
+    }
+    const int64_t total = offsets[n_clusters];
+    if ((st = check_n(total))) return st;
+    // longest first (stable, so equal sizes keep index order)
+    std::vector<int32_t> order((size_t)n_clusters);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t bb) {
+        return offsets[a + 1] - offsets[a] > offsets[bb + 1] - offsets[bb];
+    });
+    sd_batch* b = new sd_batch();
+    b->p = *p;
+    b->n_clusters = n_clusters;
+    b->total = total;
+    b->max_size = max_size;
+    if (hipGetDevice(&b->dev) != hipSuccess) {
+        delete b;
+        return fail(SD_EDEVICE, "hipGetDevice failed");
+    }
+    const size_t ob = (size_t)(n_clusters + 1) * sizeof(int64_t);
+    const size_t rb = (size_t)n_clusters * sizeof(int32_t);
+    if (hipMalloc(&b->dmem, ob + rb + 256) != hipSuccess) {
+        (void)hipGetLastError();
+        delete b;
+        return fail(SD_ENOMEM, "plan allocation failed");
+    }
+    b->d_offsets = (int64_t*)b->dmem;
+    b->d_order = (int32_t*)((char*)b->dmem + ob);
+    b->d_counter = (int32_t*)((char*)b->dmem + ((ob + rb + 63) & ~(size_t)63));
+    if (hipMemcpy(b->d_offsets, offsets, ob, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(b->d_order, order.data(), rb, hipMemcpyHostToDevice) != hipSuccess ||
+        hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking) != hipSuccess) {
+        (void)hipFree(b->dmem);
+        delete b;
+        return fail(SD_EDEVICE, "plan upload failed");
+    }
+    g_batches.push_back(b);
+    *out = b;
+    return SD_OK;
+}
+
+sd_status sd_batch_destroy(sd_batch* b)
+{
+    if (!b) return SD_OK;
+    (void)hipDeviceSynchronize();
+    drop_graph(b);
+    if (b->cap) (void)hipStreamDestroy(b->cap);
+    if (b->dmem) (void)hipFree(b->dmem);
+    g_batches.erase(std::remove(g_batches.begin(), g_batches.end(), b), g_batches.end());
+    delete b;
+    return SD_OK;
+}
+
+int64_t sd_batch_particles(const sd_batch* b)
+{
+    return b ? b->total : -1;
+}
+
+sd_status mobility_apply_batched(sd_batch* b, const void* pos, const void* force, double* vel,
+                                 int32_t precision, void* stream)
+{
+    sd_status st;
+    if ((st = check_batch(b)) || (st = check_precision(precision))) return st;
+    const size_t al = vec4_align(precision);
+    if ((st = check_ptr(pos, al, "pos")) || (st = check_ptr(force, al, "force")) ||
+        (st = check_ptr(vel, 8, "vel")))
+        return st;
+    hipStream_t hs = (hipStream_t)stream;
+    void* x64 = nullptr;
+    if ((st = ws_get(WS_STAGE, 3 * (size_t)b->total * sizeof(double), &x64))) return st;
+    const int n = (int)b->total;
+    if (precision == SD_FP64)
+        hipLaunchKernelGGL(k_unpack_f64, dim3((n + 255) / 256), dim3(256), 0, hs,
+                           (const double4*)pos, (double*)x64, n);
+    else
+        hipLaunchKernelGGL(k_unpack_f32, dim3((n + 255) / 256), dim3(256), 0, hs,
+                           (const float4*)pos, (double*)x64, n);
+    const int nwg = batch_workgroups(b, precision, SD_EULER);
+    hipError_t e = launch_fill_i32(b->d_counter, 0, 1, hs);
+    if (e == hipSuccess)
+        e = launch_batched_apply(batch_dev(b), b->p.tensor, precision, pair_const(&b->p), x64,
+                                 force, vel, nwg, hs);
+    if (e != hipSuccess) return fail(SD_EDEVICE, "batched launch: %s", hipGetErrorString(e));
+    return SD_OK;
+}
+
+sd_status sd_run_batched(sd_batch* b, double* x, const void* force, double dt, int64_t steps,
+                         int32_t integrator, int32_t precision, int32_t use_graph, void* stream)
+{
+    sd_status st;
+    if ((st = check_batch(b)) || (st = check_precision(precision))) return st;
+    if ((st = check_ptr(x, 8, "x")) || (st = check_ptr(force, vec4_align(precision), "force")))
+        return st;
+    if (!(dt > 0.0) || !std::isfinite(dt)) return fail(SD_EINVAL, "dt must be finite and > 0");
+    if (steps < 0 || steps > INT32_MAX) return fail(SD_EINVAL, "steps must be in [0, 2^31)");
+    if (integrator != SD_EULER && integrator != SD_AB2) return fail(SD_EINVAL, "unknown integrator");
+    if (steps == 0) return SD_OK;
+    hipStream_t hs = (hipStream_t)stream;
+    const int nwg = batch_workgroups(b, precision, integrator);
+    const PairConst pc = pair_const(&b->p);
+    const BatchDev d = batch_dev(b);
+    if (!use_graph) {
+        hipError_t e = launch_fill_i32(b->d_counter, 0, 1, hs);
+        if (e == hipSuccess)
+            e = launch_batched_run(d, b->p.tensor, precision, pc, x, force, dt, (int)steps,
+                                   integrator, nwg, hs);
+        if (e != hipSuccess) return fail(SD_EDEVICE, "batched launch: %s", hipGetErrorString(e));
+        return SD_OK;
+    }
+    GraphKey key;
+    key.x = x;
+    key.frc = force;
+    key.dt = dt;
+    key.steps = steps;
+    key.integ = integrator;
+    key.prec = precision;
+    key.nwg = nwg;
+    if (!b->exec || !(b->key == key)) {
+        drop_graph(b);
+        // capture [queue reset (fill kernel, no memset node), persistent kernel]
+        if (hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal) != hipSuccess)
+            return fail(SD_EDEVICE, "hipStreamBeginCapture failed");
+        hipError_t e = launch_fill_i32(b->d_counter, 0, 1, b->cap);
+        if (e == hipSuccess)
+            e = launch_batched_run(d, b->p.tensor, precision, pc, x, force, dt, (int)steps,
+                                   integrator, nwg, b->cap);
+        hipGraph_t g = nullptr;
+        hipError_t e2 = hipStreamEndCapture(b->cap, &g);
+        if (e != hipSuccess || e2 != hipSuccess || !g) {
+            if (g) (void)hipGraphDestroy(g);
+            return fail(SD_EDEVICE, "graph capture failed: %s",
+                        hipGetErrorString(e != hipSuccess ? e : e2));
+        }
+        hipGraphExec_t ex = nullptr;
+        if (hipGraphInstantiate(&ex, g, nullptr, nullptr, 0) != hipSuccess) {
+            (void)hipGraphDestroy(g);
+            return fail(SD_EDEVICE, "hipGraphInstantiate failed");
+        }
+        b->graph = g;
+        b->exec = ex;
+        b->key = key;
+    }
+    if (hipGraphLaunch(b->exec, hs) != hipSuccess) return fail(SD_EDEVICE, "hipGraphLaunch failed");
+    return SD_OK;
+}
+
+}  // extern "C"

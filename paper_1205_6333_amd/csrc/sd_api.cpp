@@ -451,6 +451,19 @@ sd_status sd_run(const sd_params* p, int64_t n, double* x, const void* force, do
     return SD_OK;
 }
 
+sd_status sd_pack(int64_t n, const double* v, void* out, int32_t precision, void* stream)
+{
+    sd_status st;
+    if ((st = check_n(n)) || (st = check_precision(precision))) return st;
+    if ((st = check_ptr(v, 8, "v")) || (st = check_ptr(out, vec4_align(precision), "out")))
+        return st;
+    hipStream_t hs = (hipStream_t)stream;
+    hipError_t e = precision == SD_FP64 ? launch_pack_f64(v, (double4*)out, (int)n, hs)
+                                        : launch_pack_f32(v, (float4*)out, (int)n, hs);
+    if (e != hipSuccess) return fail(SD_EDEVICE, "pack launch: %s", hipGetErrorString(e));
+    return SD_OK;
+}
+
 sd_status sd_set_kernel_config(int32_t precision, const sd_kernel_config* cfg)
 {
     sd_status st;

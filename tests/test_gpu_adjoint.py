@@ -1,0 +1,145 @@
+"""GPU adjoint (mobility_adjoint, sd_run_adjoint, autograd) against the FP64
+oracle's adjoint, which is itself pinned to central finite differences.
+
+Tolerances (relative 2-norm): FP64 path 1e-10; FP32-compensated path 1e-5 for
+the time-loop gradients (the target for adjoint gradients), 1e-6 for a single
+product's vector-Jacobian product."""
+import numpy as np
+import pytest
+
+from paper_1205_6333_amd import workloads as W
+
+from gpu_util import rel2, to_dev3, to_dev4
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def sd():
+    import torch
+    assert torch.cuda.is_available()
+    import paper_1205_6333_amd as sd
+    sd.lib()
+    return sd
+
+
+def _dt(sd, prec):
+    import torch
+    return torch.float64 if prec == sd.SD_FP64 else torch.float32
+
+
+@pytest.mark.parametrize("prec,tol", [(0, 1e-6), (1, 1e-11)])
+@pytest.mark.parametrize("case", ["dilute", "overlap", "oseen"])
+@pytest.mark.parametrize("n", [1, 97, 700])
+def test_mobility_adjoint_parity(sd, orc, prec, tol, case, n):
+    import torch
+    if case == "dilute":
+        x = W.random_suspension(n, phi=0.05, seed=300 + n)
+        kw = {}
+    elif case == "overlap":
+        x = np.random.default_rng(301).normal(0.0, 2.5, size=(n, 3))
+        kw = dict(overlap=True, a=1.2)
+    else:
+        x = W.random_suspension(n, phi=0.1, seed=302)
+        kw = dict(tensor=1)
+    f = W.gaussian_forces(n, seed=303)
+    lam = W.gaussian_forces(n, seed=304)
+    if prec != 1:
+        x, f, lam = W.round_to_f32(x), W.round_to_f32(f), W.round_to_f32(lam)
+    ps = sd.params(**kw)
+    po = orc.params(**kw)
+    dt = _dt(sd, prec)
+    gx, gf = sd.mobility_adjoint(to_dev4(x, dt), to_dev4(f, dt), to_dev4(lam, dt), params=ps,
+                                 precision=prec)
+    torch.cuda.synchronize()
+    ref_x = orc.mobility_vjp_x(po, x, f, lam)
+    ref_f = orc.mobility_transpose(po, x, lam)
+    if n > 1:
+        assert rel2(gx.cpu().numpy(), ref_x) <= tol
+    else:
+        assert np.all(gx.cpu().numpy() == 0.0)
+    assert rel2(gf.cpu().numpy(), ref_f) <= tol
+
+
+def _diff_case(n, steps, dt, seed=71):
+    x0 = W.random_suspension(n, phi=0.05, seed=seed)
+    F0 = W.gravity_forces(n)
+    Fp = F0 + 0.1 * W.gaussian_forces(n, seed=4)
+    return x0, F0, Fp, dt, steps
+
+
+@pytest.mark.parametrize("prec,tol", [(0, 1e-5), (1, 1e-10)])
+@pytest.mark.parametrize("every", [20, 7])
+def test_run_adjoint_fd_case(sd, orc, prec, tol, every):
+    """The n = 16, 200-step differentiation case (oracle adjoint = FD to 1e-6)."""
+    import torch
+    x0, F0, Fp, dt, steps = _diff_case(16, 200, 0.01)
+    p = orc.params()
+    xt, _, _ = orc.run(p, x0, Fp, dt, steps)
+    xN, _, _ = orc.run(p, x0, F0, dt, steps)
+    gx_ref, gf_ref = orc.run_adjoint_euler(p, x0, F0, dt, steps, 2 * (xN - xt))
+    frc = to_dev4(F0, _dt(sd, prec))
+    xd = to_dev3(x0)
+    ck = torch.empty((steps // every + 1) * 16 * 3, dtype=torch.float64, device=xd.device)
+    xe = xd.clone()
+    sd.sd_run(xe, frc, dt, steps, checkpoints=ck, checkpoint_every=every, precision=prec)
+    gN = 2 * (xe - to_dev3(xt))
+    for ckpt in (ck, None):
+        gx, gf = sd.sd_run_adjoint(xd, frc, dt, steps, gN.contiguous(), checkpoints=ckpt,
+                                   checkpoint_every=every, precision=prec)
+        torch.cuda.synchronize()
+        ex, ef = rel2(gx.cpu().numpy(), gx_ref), rel2(gf.cpu().numpy(), gf_ref)
+        print("prec=%d every=%d ckpt=%s grad_x0 %.2e grad_F %.2e" % (prec, every,
+                                                                     ckpt is not None, ex, ef))
+        assert ex <= tol and ef <= tol
+
+
+def test_run_adjoint_larger(sd, orc):
+    """n = 512, 40 steps, FP32-compensated and FP64 against the oracle adjoint."""
+    import torch
+    x0, F0, Fp, dt, steps = _diff_case(512, 40, 0.01, seed=73)
+    p = orc.params()
+    xt, _, _ = orc.run(p, x0, Fp, dt, steps)
+    xN, _, _ = orc.run(p, x0, F0, dt, steps)
+    gx_ref, gf_ref = orc.run_adjoint_euler(p, x0, F0, dt, steps, 2 * (xN - xt))
+    for prec, tol in ((0, 1e-5), (1, 1e-10)):
+        frc = to_dev4(F0, _dt(sd, prec))
+        xd = to_dev3(x0)
+        gN = to_dev3(2 * (xN - xt))
+        gx, gf = sd.sd_run_adjoint(xd, frc, dt, steps, gN, checkpoint_every=20, precision=prec)
+        torch.cuda.synchronize()
+        assert rel2(gx.cpu().numpy(), gx_ref) <= tol
+        assert rel2(gf.cpu().numpy(), gf_ref) <= tol
+
+
+def test_autograd_mobility_and_run(sd, orc):
+    import torch
+    from paper_1205_6333_amd import autograd as AG
+    n = 200
+    x = W.random_suspension(n, phi=0.05, seed=81)
+    F = W.gaussian_forces(n, seed=82)
+    g = W.gaussian_forces(n, seed=83)
+    p = orc.params()
+    for prec, tol in ((1, 1e-11), (0, 1e-6)):
+        xo = x if prec == 1 else W.round_to_f32(x)
+        Fo = F if prec == 1 else W.round_to_f32(F)
+        go = g if prec == 1 else W.round_to_f32(g)
+        xt = to_dev3(xo).requires_grad_(True)
+        Ft = to_dev3(Fo).requires_grad_(True)
+        v = AG.mobility(xt, Ft, precision=prec)
+        (v * to_dev3(go)).sum().backward()
+        assert rel2(v.detach().cpu().numpy(), orc.mobility(p, xo, Fo)) <= tol
+        assert rel2(xt.grad.cpu().numpy(), orc.mobility_vjp_x(p, xo, Fo, go)) <= tol
+        assert rel2(Ft.grad.cpu().numpy(), orc.mobility_transpose(p, xo, go)) <= tol
+    # loss through 60 Euler steps, checkpoint every 20
+    x0, F0, Fp, dt, steps = _diff_case(64, 60, 0.01, seed=84)
+    xt_ref, _, _ = orc.run(p, x0, Fp, dt, steps)
+    xN, _, _ = orc.run(p, x0, F0, dt, steps)
+    gx_ref, gf_ref = orc.run_adjoint_euler(p, x0, F0, dt, steps, 2 * (xN - xt_ref))
+    x0t = to_dev3(x0).requires_grad_(True)
+    F0t = to_dev3(F0).requires_grad_(True)
+    xe = AG.run(x0t, F0t, dt, steps, checkpoint_every=20, precision=sd.SD_FP64)
+    loss = ((xe - to_dev3(xt_ref)) ** 2).sum()
+    loss.backward()
+    assert rel2(x0t.grad.cpu().numpy(), gx_ref) <= 1e-10
+    assert rel2(F0t.grad.cpu().numpy(), gf_ref) <= 1e-10

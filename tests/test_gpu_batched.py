@@ -1,0 +1,159 @@
+"""Batched independent clusters: one persistent kernel (optionally launched
+through a captured HIP graph) against per-cluster oracle runs."""
+import numpy as np
+import pytest
+
+from paper_1205_6333_amd import workloads as W
+
+from gpu_util import rel2, to_dev3, to_dev4
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def sd():
+    import torch
+    assert torch.cuda.is_available()
+    import paper_1205_6333_amd as sd
+    sd.lib()
+    return sd
+
+
+def _dt(sd, prec):
+    import torch
+    return torch.float64 if prec == sd.SD_FP64 else torch.float32
+
+
+def _per_cluster(offsets, fn):
+    out = []
+    for c in range(len(offsets) - 1):
+        out.append(fn(offsets[c], offsets[c + 1]))
+    return np.concatenate(out, 0)
+
+
+@pytest.fixture(scope="module")
+def clusters():
+    offsets, x = W.clusters(96, nmin=4, nmax=256, seed=5)
+    return offsets, x, W.gravity_forces(len(x)) + 0.2 * W.gaussian_forces(len(x), seed=6)
+
+
+@pytest.mark.parametrize("prec,tol", [(0, 1e-6), (1, 1e-12), (2, 1e-5)])
+def test_apply_batched(sd, orc, clusters, prec, tol):
+    import torch
+    offsets, x, f = clusters
+    b = sd.Batch(offsets)
+    xo, fo = (x, f) if prec == 1 else (W.round_to_f32(x), W.round_to_f32(f))
+    v = sd.mobility_apply_batched(b, to_dev4(xo, _dt(sd, prec)), to_dev4(fo, _dt(sd, prec)),
+                                  precision=prec)
+    torch.cuda.synchronize()
+    p = orc.params()
+    ref = _per_cluster(offsets, lambda a, e: orc.mobility(p, xo[a:e], fo[a:e]))
+    assert rel2(v.cpu().numpy(), ref) <= tol
+    b.close()
+
+
+@pytest.mark.parametrize("prec,tol", [(0, 1e-6), (1, 1e-12)])
+@pytest.mark.parametrize("integ", [0, 1])
+def test_run_batched_vs_oracle(sd, orc, clusters, prec, tol, integ):
+    import torch
+    offsets, x, f = clusters
+    fo = f if prec == 1 else W.round_to_f32(f)
+    b = sd.Batch(offsets)
+    xd = to_dev3(x)
+    sd.sd_run_batched(b, xd, to_dev4(fo, _dt(sd, prec)), 0.01, 30, integrator=integ,
+                      precision=prec, use_graph=False)
+    torch.cuda.synchronize()
+    p = orc.params()
+    ref = _per_cluster(offsets, lambda a, e: orc.run(p, x[a:e], fo[a:e], 0.01, 30, integ)[0])
+    err = np.abs(xd.cpu().numpy() - ref).max() / np.abs(ref - x).max()
+    print("prec=%d integ=%d err/disp=%.3e" % (prec, integ, err))
+    assert err <= tol
+    b.close()
+
+
+def test_graph_replays_match_eager(sd, clusters):
+    """Graph launch == eager launch bitwise, over several replays with eager
+    work and synchronisations between them."""
+    import torch
+    offsets, x, f = clusters
+    b = sd.Batch(offsets)
+    frc = to_dev4(W.round_to_f32(f), torch.float32)
+    eager = to_dev3(x)
+    sd.sd_run_batched(b, eager, frc, 0.01, 10, use_graph=False)
+    xg = to_dev3(x)
+    for rep in range(4):
+        xg.copy_(to_dev3(x))
+        torch.cuda.synchronize()
+        sd.sd_run_batched(b, xg, frc, 0.01, 10, use_graph=True)
+        scratch = torch.randn(1000, device=xg.device).sum()  # unrelated eager work
+        torch.cuda.synchronize()
+        assert torch.equal(xg, eager), rep
+        assert torch.isfinite(scratch)
+    b.close()
+
+
+def test_cluster_size_edges(sd, orc):
+    """Clusters of 1, 2 and 3 particles, an empty cluster, and clusters above
+    256 (several particles per lane) up to the maximum size."""
+    import torch
+    sizes = [1, 2, 0, 3, 257, 600, 1024, 5]
+    rng = np.random.default_rng(9)
+    xs = [W._sequential_reject(lambda k: rng.normal(0, 6.0, size=(k, 3)), s, 2.2, batch=64)
+          if s else np.zeros((0, 3)) for s in sizes]
+    offsets = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    x = np.concatenate(xs, 0)
+    f = W.gravity_forces(len(x))
+    b = sd.Batch(offsets)
+    p = orc.params()
+    for prec, tol in ((0, 1e-6), (1, 1e-12)):
+        fo = f if prec == 1 else W.round_to_f32(f)
+        xo = x if prec == 1 else W.round_to_f32(x)
+        v = sd.mobility_apply_batched(b, to_dev4(xo, _dt(sd, prec)), to_dev4(fo, _dt(sd, prec)),
+                                      precision=prec)
+        xd = to_dev3(x)
+        sd.sd_run_batched(b, xd, to_dev4(fo, _dt(sd, prec)), 0.02, 12, precision=prec)
+        torch.cuda.synchronize()
+        ref_v = np.concatenate([orc.mobility(p, xo[a:e], fo[a:e]) for a, e in
+                                zip(offsets[:-1], offsets[1:]) if e > a], 0)
+        assert rel2(v.cpu().numpy(), ref_v) <= tol
+        ref_x = np.concatenate([orc.run(p, x[a:e], fo[a:e], 0.02, 12)[0] for a, e in
+                                zip(offsets[:-1], offsets[1:]) if e > a], 0)
+        assert np.abs(xd.cpu().numpy() - ref_x).max() <= tol * 100 * np.abs(ref_x - x).max()
+    b.close()
+
+
+def test_overlapping_clusters(sd, orc):
+    import torch
+    sizes = [40, 120, 7]
+    rng = np.random.default_rng(10)
+    x = rng.normal(0, 1.5, size=(sum(sizes), 3))
+    x[5] = x[6]  # coincident pair
+    offsets = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    f = W.gaussian_forces(len(x), seed=11)
+    pb = sd.params(overlap=True)
+    b = sd.Batch(offsets, params=pb)
+    p = orc.params(overlap=True)
+    for prec, tol in ((0, 1e-6), (1, 1e-12)):
+        xo = x if prec == 1 else W.round_to_f32(x)
+        fo = f if prec == 1 else W.round_to_f32(f)
+        v = sd.mobility_apply_batched(b, to_dev4(xo, _dt(sd, prec)), to_dev4(fo, _dt(sd, prec)),
+                                      precision=prec)
+        torch.cuda.synchronize()
+        ref = np.concatenate([orc.mobility(p, xo[a:e], fo[a:e]) for a, e in
+                              zip(offsets[:-1], offsets[1:])], 0)
+        assert rel2(v.cpu().numpy(), ref) <= tol
+    b.close()
+
+
+def test_autotune_installs_a_valid_config(sd, orc):
+    import torch
+    n = 3000
+    report = sd.sd_autotune(n, precision=sd.SD_FP32_KAHAN)
+    assert '"ranked"' in report
+    cfg = sd.sd_get_kernel_config(sd.SD_FP32_KAHAN, n)
+    x = W.random_suspension(n, seed=12)
+    f = W.gaussian_forces(n, seed=13)
+    xo, fo = W.round_to_f32(x), W.round_to_f32(f)
+    v = sd.mobility_apply(to_dev4(xo, torch.float32), to_dev4(fo, torch.float32))
+    torch.cuda.synchronize()
+    assert rel2(v.cpu().numpy(), orc.mobility(orc.params(), xo, fo)) <= 1e-6, cfg
