@@ -15,6 +15,16 @@ sampled rows against the FP64 oracle, the roofline of the pair kernel
 own rate on the host cores.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W]
+
+Other rows of the hot path are measured with --workload (one JSON line each):
+  timeloop  N = 65536 sedimentation, overlap-regularised RPY, AB2 dt = 0.005,
+            FP32-compensated pair kernel with FP64 positions; FP64 path as the
+            long reference (drift of the centre-of-mass velocity)
+  batched   4096 independent clusters, N_c uniform on [4, 256], 100 Euler
+            steps dt = 0.01 in one persistent graph-launched kernel
+  adjoint   N = 8192, 200 Euler steps dt = 0.01, loss |x_N - x_target|^2,
+            checkpoint every 20 steps: forward and backward times
+  copy      a plain device copy of --copy-mib MiB (calibrates HBM counters)
 """
 from __future__ import annotations
 
@@ -30,6 +40,31 @@ FLOP_PER_PAIR = 35          # canonical useful flops per pair, see the design doc
 PEAK_FP32_TFLOPS = 157.3    # MI355X published FP32 vector peak
 PEAK_FP32_NONPACKED = 78.6  # the same without packed FP32 (256 CU x 4 SIMD x 16 lanes x 2 x 2.4 GHz)
 METRIC = "G pair-interactions/s of RPY mobility product at N=65536 (FP32-comp vs FP64)"
+
+# HBM traffic of one product-kernel launch from two rocprofv3 counter passes
+# (FETCH_SIZE, WRITE_SIZE; profiles/pair_kernel_f32_n65536_hbm_counters.md), each
+# scaled by what the counter reads for a plain 256 MiB copy (fetch x 2.00,
+# write x 1.00).  Valid only for the kernel source (SHA-1 of mobility.hip) and
+# launch configuration the counters were taken with; otherwise reported as null.
+PMC_TRAFFIC = {"source_sha1": "c0e6b20db863c9299885a8250a19b38d5c1bebec",
+               "n": 65536,
+               "config": {"variant": 0, "block": 256, "splits": 32, "ilp": 1, "kahan_block": 4},
+               "fetch_kib": 4657.0, "write_kib": 49152.0, "fetch_scale": 2.0, "write_scale": 1.0}
+
+
+def _measured_traffic(n, cfg):
+    """HBM bytes per product-kernel launch, or None if the counters are stale."""
+    import hashlib
+    src = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_1205_6333_amd", "csrc",
+                       "mobility.hip")
+    try:
+        sha = hashlib.sha1(open(src, "rb").read()).hexdigest()
+    except OSError:
+        return None
+    m = PMC_TRAFFIC
+    if sha != m["source_sha1"] or n != m["n"] or dict(cfg) != m["config"]:
+        return None
+    return 1024.0 * (m["fetch_kib"] * m["fetch_scale"] + m["write_kib"] * m["write_scale"])
 
 
 def _to4(v, dtype, device):
@@ -86,6 +121,130 @@ def cpu_baseline(x32, f32, vgpu, n, target_s):
                                                                           len(rows) * n, dt)}, err
 
 
+def _sync_time(fn):
+    import torch
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    fn()
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0
+
+
+def run_timeloop(args, sd, W, dev):
+    import torch
+    n = args.n
+    steps = args.loop_steps
+    x0 = W.random_suspension(n, phi=0.05, seed=1)
+    f = W.gravity_forces(n)
+    p = sd.params(overlap=True)
+    out = {"metric": "AB2 sedimentation steps/s at N=%d (FP32-comp pair kernel, FP64 positions)" % n,
+           "unit": "steps/s", "n_gpus": 1, "higher_is_better": True, "dtype": "f32",
+           "data": "synthetic",
+           "config": {"workload": "sedimentation, N=%d, random suspension phi=0.05, F=(0,0,-1), "
+                                  "overlap-regularised RPY, AB2 dt=0.005, %d steps" % (n, steps)}}
+    res = {}
+    for prec in (sd.SD_FP32_KAHAN, sd.SD_FP64):
+        dt4 = torch.float64 if prec == sd.SD_FP64 else torch.float32
+        frc = _to4(f, dt4, dev)
+        x = torch.tensor(x0, device=dev)
+        vp = torch.zeros_like(x)
+        sd.sd_run(x, frc, 0.005, 3, v_prev=vp, integrator=sd.SD_AB2, params=p, precision=prec)
+        x = torch.tensor(x0, device=dev)
+        vcm = []
+        chunk = max(1, steps // 20)
+
+        def go():
+            done = 0
+            while done < steps:
+                k = min(chunk, steps - done)
+                sd.sd_run(x, frc, 0.005, k, step0=done, v_prev=vp, integrator=sd.SD_AB2,
+                          params=p, precision=prec)
+                done += k
+                vcm.append(sd.sd_mean_vector(vp))
+        t = _sync_time(go)
+        res[prec] = (t, x.cpu().numpy(), torch.stack(vcm).cpu().numpy())
+    t32, x32, v32 = res[sd.SD_FP32_KAHAN]
+    t64, x64, v64 = res[sd.SD_FP64]
+    out.update({"value": steps / t32, "steps": steps, "ms_per_step": t32 * 1e3 / steps,
+                "g_pairs_per_s": float(n) * n * steps / t32 / 1e9,
+                "fp64_steps_per_s": steps / t64, "speedup_vs_fp64": t64 / t32,
+                "vcm_z_final": float(v32[-1, 2]), "vcm_z_final_fp64": float(v64[-1, 2]),
+                "vcm_drift_vs_fp64_max": float(np.abs(v32 - v64).max()),
+                "x_final_vs_fp64_max_abs": float(np.abs(x32 - x64).max())})
+    return out
+
+
+def run_batched(args, sd, W, dev):
+    import torch
+    offsets, x0 = W.clusters(4096, nmin=4, nmax=256, sigma=4.0, seed=3)
+    sizes = np.diff(offsets)
+    pairs = float((sizes.astype(np.float64) ** 2).sum())
+    f = W.gravity_forces(len(x0))
+    frc = _to4(f, torch.float32, dev)
+    b = sd.Batch(offsets)
+    x = torch.tensor(x0, device=dev)
+    steps = 100
+    sd.sd_run_batched(b, x, frc, 0.01, steps, use_graph=True)  # capture + warm-up
+    times = []
+    for _ in range(max(1, args.steps // 4)):
+        x.copy_(torch.tensor(x0, device=dev))
+        times.append(_sync_time(lambda: sd.sd_run_batched(b, x, frc, 0.01, steps,
+                                                          use_graph=True)))
+    t = float(np.median(times))
+    return {"metric": "G pair-interactions/s of batched clusters (4096 clusters, 100 Euler steps)",
+            "value": pairs * steps / t / 1e9, "unit": "G pair-interactions/s", "n_gpus": 1,
+            "higher_is_better": True, "dtype": "f32", "data": "synthetic",
+            "ms_per_launch": t * 1e3, "launches_timed": len(times),
+            "config": {"workload": "4096 free-space clusters, N_c~U{4..256} (seed 3), Gaussian "
+                                   "sigma=4a with rejection < 2.2a, F=(0,0,-1), Euler dt=0.01, "
+                                   "100 steps in one persistent HIP-graph launch",
+                       "particles": int(offsets[-1]), "sum_nc2": pairs}}
+
+
+def run_adjoint(args, sd, W, dev):
+    import torch
+    from paper_1205_6333_amd import autograd as AG
+    n, steps = 8192, 200
+    x0 = W.random_suspension(n, phi=0.05, seed=1)
+    F0 = W.gravity_forces(n)
+    Fp = F0 + 0.1 * W.gaussian_forces(n, seed=4)
+    out = {"metric": "backward/forward time ratio of the checkpointed Euler adjoint at N=8192",
+           "unit": "ratio", "n_gpus": 1, "higher_is_better": False, "dtype": "f32",
+           "data": "synthetic",
+           "config": {"workload": "N=8192 random suspension phi=0.05, 200 Euler steps dt=0.01, "
+                                  "loss |x_N - x_target|^2, x_target from forces F0 + 0.1 N(0,1), "
+                                  "checkpoint every 20 steps"}}
+    xt = torch.tensor(x0, device=dev)
+    sd.sd_run(xt, _to4(Fp, torch.float32, dev), 0.01, steps)
+    x0t = torch.tensor(x0, device=dev, requires_grad=True)
+    F0t = torch.tensor(F0, device=dev, requires_grad=True)
+    xe = AG.run(x0t, F0t, 0.01, steps, checkpoint_every=20)  # warm-up
+    ((xe - xt) ** 2).sum().backward()
+    holder = {}
+
+    def fwd():
+        holder["xe"] = AG.run(x0t, F0t, 0.01, steps, checkpoint_every=20)
+
+    def bwd():
+        ((holder["xe"] - xt) ** 2).sum().backward()
+    tf = _sync_time(fwd)
+    tb = _sync_time(bwd)
+    out.update({"value": tb / tf, "forward_s": tf, "backward_s": tb,
+                "forward_g_pairs_per_s": float(n) * n * steps / tf / 1e9})
+    return out
+
+
+def run_copy(args, dev):
+    import torch
+    m = int(args.copy_mib * 2 ** 20 // 4)
+    src = torch.ones(m, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    return {"metric": "device copy", "bytes_per_copy": 4 * m, "copies": 3}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -97,6 +256,10 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 GPU path")
     ap.add_argument("--tune", action="store_true", help="autotune the kernel shape first (untimed)")
+    ap.add_argument("--workload", default="product",
+                    choices=["product", "timeloop", "batched", "adjoint", "copy"])
+    ap.add_argument("--loop-steps", type=int, default=1000, help="steps of --workload timeloop")
+    ap.add_argument("--copy-mib", type=float, default=256.0)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the product is not sharded across GPUs in this "
@@ -109,6 +272,13 @@ def main():
 
     dev = torch.device("cuda", 0)
     n = args.n
+    if args.workload != "product":
+        fn = {"timeloop": lambda: run_timeloop(args, sd, W, dev),
+              "batched": lambda: run_batched(args, sd, W, dev),
+              "adjoint": lambda: run_adjoint(args, sd, W, dev),
+              "copy": lambda: run_copy(args, dev)}[args.workload]
+        print(json.dumps(fn()))
+        return 0
     print("bench: generating inputs n=%d" % n, file=sys.stderr, flush=True)
     x = W.random_suspension(n, phi=0.05, seed=1)
     f = W.gaussian_forces(n, seed=2)
@@ -138,7 +308,8 @@ def main():
     }
     achieved = FLOP_PER_PAIR * pairs / (kern_ms * 1e-3) / 1e12
     out["roofline"] = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS,
-                       "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None,
+                       "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_TFLOPS,
+                       "traffic": _measured_traffic(n, cfg),
                        "flop_per_pair": FLOP_PER_PAIR,
                        "frac_of_nonpacked_peak": achieved / PEAK_FP32_NONPACKED,
                        "kernel": "pair kernel (k_pair_f32_*)"}

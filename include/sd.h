@@ -240,6 +240,16 @@ sd_status sd_profile_enable(int32_t on);
 sd_status sd_profile_read(int64_t* launches, double* total_ms);
 sd_status sd_profile_reset(void);
 
+/* -------------------------------------------------------------- observables */
+
+/*
+ * sd_mean_vector -- out[0..2] = (1/n) sum_i v_i for v f64[3n] (e.g. the
+ * centre-of-mass velocity of the sedimenting suspensions of Secs. 3.3 and 4).
+ * One work-group sums in a fixed order: the result is deterministic.
+ * out: device f64[3].
+ */
+sd_status sd_mean_vector(int64_t n, const double* v, double* out, void* stream);
+
 /* --------------------------------------------------------------------- misc */
 
 /*

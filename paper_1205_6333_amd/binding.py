@@ -75,6 +75,7 @@ def lib() -> ctypes.CDLL:
             "sd_get_kernel_config": [i32, i64, ctypes.POINTER(SdKernelConfig)],
             "sd_autotune": [P, i64, i32, vp, ctypes.c_char_p, i64],
             "sd_pack": [i64, dp, vp, i32, vp],
+            "sd_mean_vector": [i64, dp, dp, vp],
             "sd_profile_enable": [i32],
             "sd_profile_read": [ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double)],
             "sd_profile_reset": [],
@@ -310,6 +311,18 @@ def sd_pack(v, precision: int = SD_FP32_KAHAN, out=None, stream=None):
                           device=v.device)
     _vec4(out, prec, "out")
     check(lib().sd_pack(n, _ptr(v), _ptr(out), prec, _stream(stream)))
+    return out
+
+
+def sd_mean_vector(v, out=None, stream=None):
+    """(1/n) sum_i v_i of an (n, 3) float64 CUDA tensor, as a (3,) tensor."""
+    import torch
+    n = v.shape[0]
+    _vec3(v, n, "v")
+    if out is None:
+        out = torch.empty(3, dtype=torch.float64, device=v.device)
+    _vec3(out, 1, "out")
+    check(lib().sd_mean_vector(n, _ptr(v), _ptr(out), _stream(stream)))
     return out
 
 

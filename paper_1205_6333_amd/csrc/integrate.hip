@@ -107,6 +107,40 @@ __global__ void __launch_bounds__(64) k_fill_i32(int32_t* __restrict__ p, int32_
     if (k < count) p[k] = value;
 }
 
+// out = (1/n) sum_i v_i with one 256-lane work-group: lane t sums i = t, t+256,
+// ... in order, then a fixed-shape tree combines the 256 partial sums.
+__global__ void __launch_bounds__(256) k_mean_vector(const double* __restrict__ v, int64_t n,
+                                                     double* __restrict__ out)
+{
+    __shared__ double red[3][256];
+    const int t = threadIdx.x;
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+    for (int64_t i = t; i < n; i += 256) {
+        a0 += v[3 * i];
+        a1 += v[3 * i + 1];
+        a2 += v[3 * i + 2];
+    }
+    red[0][t] = a0;
+    red[1][t] = a1;
+    red[2][t] = a2;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (t < w) {
+            red[0][t] += red[0][t + w];
+            red[1][t] += red[1][t + w];
+            red[2][t] += red[2][t + w];
+        }
+        __syncthreads();
+    }
+    if (t < 3) out[t] = red[t][0] / (double)n;
+}
+
+hipError_t launch_mean_vector(const double* v, int64_t n, double* out, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_mean_vector, dim3(1), dim3(256), 0, st, v, n, out);
+    return hipGetLastError();
+}
+
 static inline dim3 grid_for(int64_t n) { return dim3((unsigned)((n + 255) / 256)); }
 
 hipError_t launch_stage_f32(const double* x, float4* pos, int n, hipStream_t st)

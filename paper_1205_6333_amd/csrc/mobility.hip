@@ -52,6 +52,24 @@ PairLaunch shape_pair_launch(int n, int variant, int block, int splits, int ilp)
     return L;
 }
 
+// Work-group -> (i-block, j-split).  Work-groups are dispatched round-robin
+// over the 8 XCDs (linear id L runs on XCD L mod 8), each with its own L2.
+// When the split count is a multiple of 8, split s is only ever handled by
+// XCD s mod 8, so every XCD streams 1/8 of the j data through its L2.
+__device__ __forceinline__ void map_block(int S, int& ib, int& s)
+{
+    const int L = blockIdx.x;
+    if ((S & 7) == 0) {
+        const int per = S >> 3;
+        const int r = L >> 3;
+        s = (r % per) * 8 + (L & 7);
+        ib = r / per;
+    } else {
+        s = L % S;
+        ib = L / S;
+    }
+}
+
 // Placeholders for padded lanes / padded tile slots.  Far apart, zero force:
 // every term they produce is exactly zero or never stored, and never NaN.
 #define SD_FAR_I (-1.0e15f)
@@ -247,9 +265,10 @@ __device__ __forceinline__ void pair_group(LaneF32 (&L)[ILP], const float4 (&pj)
 }
 
 template <int ILP, int BLOCK>
-__device__ __forceinline__ void lanes_init(LaneF32 (&L)[ILP], const float4* __restrict__ pos, int n)
+__device__ __forceinline__ void lanes_init(LaneF32 (&L)[ILP], const float4* __restrict__ pos, int n,
+                                           int ib)
 {
-    const int ibase = blockIdx.x * (BLOCK * ILP) + threadIdx.x;
+    const int ibase = ib * (BLOCK * ILP) + threadIdx.x;
 #pragma unroll
     for (int q = 0; q < ILP; ++q) {
         const int i = ibase + q * BLOCK;
@@ -293,15 +312,16 @@ constexpr int GROUP_U = 4;
 template <int TENSOR, int ACC, int BLOCK, int ILP>
 __global__ void __launch_bounds__(BLOCK)
 k_pair_f32_lds(const float4* __restrict__ pos, const float4* __restrict__ frc,
-               const double* __restrict__ x64, int n, int jchunk, PairConst pc,
+               const double* __restrict__ x64, int n, int jchunk, int S, PairConst pc,
                double* __restrict__ partial)
 {
     __shared__ float4 s_pos[BLOCK];
     __shared__ float4 s_frc[BLOCK];
+    int ib, s;
+    map_block(S, ib, s);
     LaneF32 L[ILP];
-    lanes_init<ILP, BLOCK>(L, pos, n);
+    lanes_init<ILP, BLOCK>(L, pos, n, ib);
     const int tid = threadIdx.x;
-    const int s = blockIdx.y;
     const int jbeg = s * jchunk;
     const int jend = min(n, jbeg + jchunk);
     const float gamma = pc.gamma_f, m3g = pc.m3gamma_f, thr2 = pc.thr2_f;
@@ -346,12 +366,13 @@ k_pair_f32_lds(const float4* __restrict__ pos, const float4* __restrict__ frc,
 template <int TENSOR, int ACC, int BLOCK, int ILP>
 __global__ void __launch_bounds__(BLOCK)
 k_pair_f32_smem(const float4* __restrict__ pos, const float4* __restrict__ frc,
-                const double* __restrict__ x64, int n, int jchunk, PairConst pc,
+                const double* __restrict__ x64, int n, int jchunk, int S, PairConst pc,
                 double* __restrict__ partial)
 {
+    int ib, s;
+    map_block(S, ib, s);
     LaneF32 L[ILP];
-    lanes_init<ILP, BLOCK>(L, pos, n);
-    const int s = blockIdx.y;
+    lanes_init<ILP, BLOCK>(L, pos, n, ib);
     const int jbeg = s * jchunk;
     const int jend = min(n, jbeg + jchunk);
     const float gamma = pc.gamma_f, m3g = pc.m3gamma_f, thr2 = pc.thr2_f;
@@ -380,13 +401,14 @@ k_pair_f32_smem(const float4* __restrict__ pos, const float4* __restrict__ frc,
 template <int TENSOR, int BLOCK>
 __global__ void __launch_bounds__(BLOCK)
 k_pair_f64_lds(const double4* __restrict__ pos, const double4* __restrict__ frc, int n, int jchunk,
-               PairConst pc, double* __restrict__ partial)
+               int S, PairConst pc, double* __restrict__ partial)
 {
     __shared__ double4 s_pos[BLOCK];
     __shared__ double4 s_frc[BLOCK];
+    int ib, s;
+    map_block(S, ib, s);
     const int tid = threadIdx.x;
-    const int i = blockIdx.x * BLOCK + tid;
-    const int s = blockIdx.y;
+    const int i = ib * BLOCK + tid;
     double xi0 = -1.0e15, xi1 = -1.0e15, xi2 = -1.0e15;
     if (i < n) {
         const double4 p = pos[i];
@@ -482,13 +504,13 @@ static hipError_t launch_f32_t(const PairLaunch& L, const float4* pos, const flo
                                hipStream_t st)
 {
     const int iblocks = (n + BLOCK * ILP - 1) / (BLOCK * ILP);
-    dim3 grid(iblocks, L.splits), block(BLOCK);
+    dim3 grid(iblocks * L.splits), block(BLOCK);
     if (L.variant == 1)
         hipLaunchKernelGGL((k_pair_f32_smem<TENSOR, ACC, BLOCK, ILP>), grid, block, 0, st, pos,
-                           frc, x64, n, L.jchunk, pc, partial);
+                           frc, x64, n, L.jchunk, L.splits, pc, partial);
     else
         hipLaunchKernelGGL((k_pair_f32_lds<TENSOR, ACC, BLOCK, ILP>), grid, block, 0, st, pos,
-                           frc, x64, n, L.jchunk, pc, partial);
+                           frc, x64, n, L.jchunk, L.splits, pc, partial);
     return hipGetLastError();
 }
 
@@ -527,9 +549,9 @@ template <int TENSOR, int BLOCK>
 static hipError_t launch_f64_t(const PairLaunch& L, const double4* pos, const double4* frc, int n,
                                const PairConst& pc, double* partial, hipStream_t st)
 {
-    dim3 grid((n + BLOCK - 1) / BLOCK, L.splits), block(BLOCK);
+    dim3 grid(((n + BLOCK - 1) / BLOCK) * L.splits), block(BLOCK);
     hipLaunchKernelGGL((k_pair_f64_lds<TENSOR, BLOCK>), grid, block, 0, st, pos, frc, n, L.jchunk,
-                       pc, partial);
+                       L.splits, pc, partial);
     return hipGetLastError();
 }
 

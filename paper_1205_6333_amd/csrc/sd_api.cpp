@@ -189,14 +189,15 @@ sd_kernel_config default_config(int32_t prec, int64_t n)
         c.variant = 0;
         c.kahan_block = 0;
     }
-    // enough work-groups for two rounds of 4 resident waves per SIMD
+    // about 32 waves per SIMD over the launch (several rounds of resident
+    // waves, so the last round's imbalance is a small fraction of the run)
     const int cus = device_cus();
     const int64_t iblocks = (n + c.block * c.ilp - 1) / (c.block * c.ilp);
-    const int64_t target = (int64_t)cus * (16 / (c.block / 64)) * 2;
+    const int64_t target = (int64_t)cus * 4 * 32 / (c.block / 64);
     int64_t s = std::max<int64_t>(1, (target + iblocks - 1) / iblocks);
     const int64_t tiles = (n + c.block - 1) / c.block;
     s = std::min<int64_t>(s, tiles);
-    s = std::min<int64_t>(s, 256);
+    s = std::min<int64_t>(s, 512);
     c.splits = (int32_t)s;
     return c;
 }
@@ -461,6 +462,16 @@ sd_status sd_pack(int64_t n, const double* v, void* out, int32_t precision, void
     hipError_t e = precision == SD_FP64 ? launch_pack_f64(v, (double4*)out, (int)n, hs)
                                         : launch_pack_f32(v, (float4*)out, (int)n, hs);
     if (e != hipSuccess) return fail(SD_EDEVICE, "pack launch: %s", hipGetErrorString(e));
+    return SD_OK;
+}
+
+sd_status sd_mean_vector(int64_t n, const double* v, double* out, void* stream)
+{
+    sd_status st;
+    if ((st = check_n(n)) || (st = check_ptr(v, 8, "v")) || (st = check_ptr(out, 8, "out")))
+        return st;
+    hipError_t e = launch_mean_vector(v, n, out, (hipStream_t)stream);
+    if (e != hipSuccess) return fail(SD_EDEVICE, "mean launch: %s", hipGetErrorString(e));
     return SD_OK;
 }
 
