@@ -212,8 +212,8 @@ typedef struct sd_kernel_config {
     int32_t splits;       /* j-range splits (>= 1): extra work-groups per i-block */
     int32_t ilp;          /* particles i per lane (1 or 2) */
     int32_t kahan_block;  /* SD_FP32_KAHAN: pair terms summed in FP32 before each
-                             compensated add (1 = per term, 2 or 4); 0 for the
-                             other precisions */
+                             compensated add (1 = per term, 2, 4, or 8 with
+                             block >= 128); 0 for the other precisions */
 } sd_kernel_config;
 
 /* Force a configuration for a precision (NULL restores automatic choice). */

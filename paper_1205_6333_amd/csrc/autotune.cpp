@@ -44,10 +44,11 @@ std::vector<sd_kernel_config> candidates(int32_t prec, int64_t n)
             for (int ilp : { 1, 2 }) {
                 if (prec == SD_FP64 && ilp != 1) continue;
                 std::vector<int> kbs;
-                if (prec == SD_FP32_KAHAN) kbs = { 1, 2, 4 };
+                if (prec == SD_FP32_KAHAN) kbs = { 1, 2, 4, 8 };
                 else kbs = { 0 };
                 for (int kb : kbs)
                     for (int s : split_opts) {
+                        if (kb == 8 && block < 128) continue;
                         // keep the same number of j-tiles per split across block sizes
                         int splits = std::max(1, (int)((int64_t)s * 256 / block));
                         const int64_t tiles = (n + block - 1) / block;

@@ -93,7 +93,7 @@ __device__ __forceinline__ void b_near(const PairConst& pc, double d0, double d1
 
 // Velocity (pair part, physical units, self term excluded) of particle i from
 // the j = sub, sub + P, ... of the cluster held in LDS.
-// PREC: 0 FP32 + Kahan (per term), 2 FP32 plain, 1 FP64.
+// PREC: SD_FP32_KAHAN (Kahan once per group of 4 terms), SD_FP32_PLAIN, SD_FP64.
 template <int TENSOR, int PREC>
 __device__ __forceinline__ void b_velocity(int i, int sub, int P, int nc, const double* xs,
                                            const void* fsv, const float4* pf, const PairConst& pc,
@@ -129,11 +129,69 @@ __device__ __forceinline__ void b_velocity(int i, int sub, int P, int nc, const 
         v[2] = pc.alpha * a2 + nv[2];
         return;
     }
+    constexpr bool KAHAN = PREC == SD_FP32_KAHAN;
     const float4* fs = (const float4*)fsv;
     const float4 pi = pf[i];
     const float gamma = pc.gamma_f, m3g = pc.m3gamma_f, thr2 = pc.thr2_f;
     float s0 = 0.f, s1 = 0.f, s2 = 0.f, c0 = 0.f, c1 = 0.f, c2 = 0.f;
-    for (int j = sub; j < nc; j += P) {
+    // groups of 4 j (j, j + P, j + 2P, j + 3P): one near test per group; pairs
+    // below the threshold are evaluated in FP64 from the FP64 positions and get
+    // r^2 = +inf (an exact zero) in the FP32 code; Kahan once per group
+    int j = sub;
+    for (; j + 3 * P < nc; j += 4 * P) {
+        float4 pj[4], fj[4];
+        float dx[4], dy[4], dz[4], r2[4];
+        float rmin = 3.0e38f;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            pj[u] = pf[j + u * P];
+            fj[u] = fs[j + u * P];
+            dx[u] = pi.x - pj[u].x;
+            dy[u] = pi.y - pj[u].y;
+            dz[u] = pi.z - pj[u].z;
+            r2[u] = fmaf(dx[u], dx[u], fmaf(dy[u], dy[u], dz[u] * dz[u]));
+            rmin = fminf(rmin, r2[u]);
+        }
+        if (__builtin_amdgcn_ballot_w64(rmin < thr2) != 0) {
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int jj = j + u * P;
+                if (r2[u] < thr2 && jj != i)
+                    b_near<TENSOR>(pc, xs[3 * i] - xs[3 * jj], xs[3 * i + 1] - xs[3 * jj + 1],
+                                   xs[3 * i + 2] - xs[3 * jj + 2], fj[u].x, fj[u].y, fj[u].z, nv);
+                r2[u] = (r2[u] < thr2) ? __builtin_inff() : r2[u];
+            }
+        }
+        float y0 = KAHAN ? -c0 : s0, y1 = KAHAN ? -c1 : s1, y2 = KAHAN ? -c2 : s2;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const float rinv = __builtin_amdgcn_rsqf(r2[u]);
+            const float rinv2 = rinv * rinv, rinv3 = rinv2 * rinv;
+            float A = rinv, Bt = rinv3;
+            if (TENSOR == T_RPY) {
+                A = fmaf(gamma, rinv3, rinv);
+                Bt = rinv3 * fmaf(m3g, rinv2, 1.0f);
+            }
+            const float sB = Bt * fmaf(dx[u], fj[u].x, fmaf(dy[u], fj[u].y, dz[u] * fj[u].z));
+            y0 = fmaf(A, fj[u].x, fmaf(sB, dx[u], y0));
+            y1 = fmaf(A, fj[u].y, fmaf(sB, dy[u], y1));
+            y2 = fmaf(A, fj[u].z, fmaf(sB, dz[u], y2));
+        }
+        if (KAHAN) {
+            const float t0 = s0 + y0, t1 = s1 + y1, t2 = s2 + y2;
+            c0 = (t0 - s0) - y0;
+            c1 = (t1 - s1) - y1;
+            c2 = (t2 - s2) - y2;
+            s0 = t0;
+            s1 = t1;
+            s2 = t2;
+        } else {
+            s0 = y0;
+            s1 = y1;
+            s2 = y2;
+        }
+    }
+    for (; j < nc; j += P) {
         const float4 pj = pf[j];
         const float4 fj = fs[j];
         const float dx = pi.x - pj.x, dy = pi.y - pj.y, dz = pi.z - pj.z;
@@ -152,7 +210,7 @@ __device__ __forceinline__ void b_velocity(int i, int sub, int P, int nc, const 
             Bt = rinv3 * fmaf(m3g, rinv2, 1.0f);
         }
         const float sB = Bt * fmaf(dx, fj.x, fmaf(dy, fj.y, dz * fj.z));
-        if (PREC == SD_FP32_KAHAN) {
+        if (KAHAN) {
             const float y0 = fmaf(A, fj.x, fmaf(sB, dx, -c0));
             const float y1 = fmaf(A, fj.y, fmaf(sB, dy, -c1));
             const float y2 = fmaf(A, fj.z, fmaf(sB, dz, -c2));

@@ -184,18 +184,47 @@ __device__ __forceinline__ void pair_f32(LaneF32& L, const float4 pj, const floa
     }
 }
 
+// FP64 evaluation of one near pair (r^2 below the threshold) of lane particle
+// i, accumulated into the lane's own LDS slot (only the owning lane ever
+// touches it, so no synchronisation is needed and the order is fixed).  The
+// self pair and padded slots contribute nothing.
+template <int TENSOR>
+__device__ __forceinline__ void near_pair_lds(const LaneF32& L, const float4 pj, const float4 fj,
+                                           int jg, int n, const PairConst& pc,
+                                           const double* __restrict__ x64, double* slot, int stride)
+{
+    if (jg == L.i || L.i >= n || jg >= n) return;
+    double d0, d1, d2;
+    if (x64) {
+        d0 = x64[3 * (size_t)L.i + 0] - x64[3 * (size_t)jg + 0];
+        d1 = x64[3 * (size_t)L.i + 1] - x64[3 * (size_t)jg + 1];
+        d2 = x64[3 * (size_t)L.i + 2] - x64[3 * (size_t)jg + 2];
+    } else {
+        d0 = (double)L.x - (double)pj.x;
+        d1 = (double)L.y - (double)pj.y;
+        d2 = (double)L.z - (double)pj.z;
+    }
+    double n0 = slot[0], n1 = slot[stride], n2 = slot[2 * stride];
+    near_term<TENSOR>(pc, d0, d1, d2, (double)fj.x, (double)fj.y, (double)fj.z, n0, n1, n2);
+    slot[0] = n0;
+    slot[stride] = n1;
+    slot[2 * stride] = n2;
+}
+
 // A group of U pairs (i, j_0..j_{U-1}) for every lane particle.  The near test
-// is done once per group: if no lane of the wave has a pair below the
-// threshold, the unmasked fast path runs; otherwise every pair of the group
-// takes the masked path (pair_f32), which also handles the self pair.
+// is done once per group: only if some lane of the wave has a pair below the
+// threshold does the group take the rare branch, which evaluates those pairs
+// in FP64 (near_pair_lds) and sets their r^2 to +inf, so that the FP32 code
+// below gives them rinv = 0 and an exact zero contribution.  The FP32 code is
+// the same for every group.
 // ACC: 0 = plain FP32 sums, k >= 1 = Kahan compensation applied once per k
 // consecutive terms (k = 1: per term).
 template <int TENSOR, int ACC, int U, int ILP>
 __device__ __forceinline__ void pair_group(LaneF32 (&L)[ILP], const float4 (&pj)[U],
                                            const float4 (&fj)[U], int jg0, int n,
-                                           const PairConst& pc,
-                                           float gamma, float m3g, float thr2,
-                                           const double* __restrict__ x64)
+                                           const PairConst& pc, float gamma, float m3g,
+                                           float thr2, const double* __restrict__ x64,
+                                           double* near_slot, int stride)
 {
     float dx[ILP][U], dy[ILP][U], dz[ILP][U], r2[ILP][U];
     float rmin = 3.0e38f;
@@ -211,12 +240,14 @@ __device__ __forceinline__ void pair_group(LaneF32 (&L)[ILP], const float4 (&pj)
         }
     if (__builtin_amdgcn_ballot_w64(rmin < thr2) != 0) {
 #pragma unroll
-        for (int u = 0; u < U; ++u)
+        for (int q = 0; q < ILP; ++q)
 #pragma unroll
-            for (int q = 0; q < ILP; ++q)
-                pair_f32<TENSOR, ACC != 0>(L[q], pj[u], fj[u], jg0 + u, n, pc, gamma, m3g, thr2,
-                                           x64);
-        return;
+            for (int u = 0; u < U; ++u) {
+                if (r2[q][u] < thr2)
+                    near_pair_lds<TENSOR>(L[q], pj[u], fj[u], jg0 + u, n, pc, x64,
+                                          near_slot + q * (stride / ILP), stride);
+                r2[q][u] = (r2[q][u] < thr2) ? __builtin_inff() : r2[q][u];
+            }
     }
 #pragma unroll
     for (int q = 0; q < ILP; ++q) {
@@ -287,23 +318,42 @@ __device__ __forceinline__ void lanes_init(LaneF32 (&L)[ILP], const float4* __re
     }
 }
 
+// near_slot: this lane's LDS near-pair sums (component k of particle q at
+// near_slot[k * stride + q * stride / ILP]).
 template <int ILP>
 __device__ __forceinline__ void lanes_store(const LaneF32 (&L)[ILP], int n, int s, double alpha,
+                                            const double* near_slot, int stride,
                                             double* __restrict__ partial)
 {
 #pragma unroll
     for (int q = 0; q < ILP; ++q) {
         const int i = L[q].i;
+        const double* ns = near_slot + q * (stride / ILP);
         if (i < n) {
             const size_t base = (size_t)s * 3 * (size_t)n + (size_t)i;
-            partial[base] = alpha * ((double)L[q].s0 - (double)L[q].c0) + L[q].n0;
-            partial[base + (size_t)n] = alpha * ((double)L[q].s1 - (double)L[q].c1) + L[q].n1;
-            partial[base + 2 * (size_t)n] = alpha * ((double)L[q].s2 - (double)L[q].c2) + L[q].n2;
+            partial[base] = alpha * ((double)L[q].s0 - (double)L[q].c0) + (L[q].n0 + ns[0]);
+            partial[base + (size_t)n] =
+                alpha * ((double)L[q].s1 - (double)L[q].c1) + (L[q].n1 + ns[stride]);
+            partial[base + 2 * (size_t)n] =
+                alpha * ((double)L[q].s2 - (double)L[q].c2) + (L[q].n2 + ns[2 * stride]);
         }
     }
 }
 
-constexpr int GROUP_U = 4;
+template <int ILP, int BLOCK>
+__device__ __forceinline__ double* near_slots_init(double* s_near)
+{
+    double* slot = s_near + threadIdx.x;
+#pragma unroll
+    for (int k = 0; k < 3 * ILP; ++k) slot[k * BLOCK] = 0.0;
+    return slot;
+}
+
+// pairs per near test; a Kahan block of 8 terms uses groups of 8
+template <int ACC>
+struct GroupSize {
+    static constexpr int value = ACC > 4 ? ACC : 4;
+};
 
 // Variant 0: the work-group stages tiles of BLOCK j-particles (position and
 // force, 32 B each) in LDS with coalesced 16-byte loads; the next tile is
@@ -317,10 +367,14 @@ k_pair_f32_lds(const float4* __restrict__ pos, const float4* __restrict__ frc,
 {
     __shared__ float4 s_pos[BLOCK];
     __shared__ float4 s_frc[BLOCK];
+    __shared__ double s_near[3 * BLOCK * ILP];
     int ib, s;
     map_block(S, ib, s);
     LaneF32 L[ILP];
     lanes_init<ILP, BLOCK>(L, pos, n, ib);
+    double* near_slot = near_slots_init<ILP, BLOCK>(s_near);
+    constexpr int NS = BLOCK * ILP;
+    constexpr int GROUP_U = GroupSize<ACC>::value;
     const int tid = threadIdx.x;
     const int jbeg = s * jchunk;
     const int jend = min(n, jbeg + jchunk);
@@ -353,10 +407,10 @@ k_pair_f32_lds(const float4* __restrict__ pos, const float4* __restrict__ frc,
                 fj[u] = s_frc[k + u];
             }
             pair_group<TENSOR, ACC, GROUP_U, ILP>(L, pj, fj, jt + k, n, pc, gamma, m3g, thr2,
-                                                  x64);
+                                                  x64, near_slot, NS);
         }
     }
-    lanes_store<ILP>(L, n, s, pc.alpha, partial);
+    lanes_store<ILP>(L, n, s, pc.alpha, near_slot, NS, partial);
 }
 
 // Variant 1: no LDS.  The j index is wave-uniform, so positions and forces of
@@ -369,10 +423,14 @@ k_pair_f32_smem(const float4* __restrict__ pos, const float4* __restrict__ frc,
                 const double* __restrict__ x64, int n, int jchunk, int S, PairConst pc,
                 double* __restrict__ partial)
 {
+    __shared__ double s_near[3 * BLOCK * ILP];
     int ib, s;
     map_block(S, ib, s);
     LaneF32 L[ILP];
     lanes_init<ILP, BLOCK>(L, pos, n, ib);
+    double* near_slot = near_slots_init<ILP, BLOCK>(s_near);
+    constexpr int NS = BLOCK * ILP;
+    constexpr int GROUP_U = GroupSize<ACC>::value;
     const int jbeg = s * jchunk;
     const int jend = min(n, jbeg + jchunk);
     const float gamma = pc.gamma_f, m3g = pc.m3gamma_f, thr2 = pc.thr2_f;
@@ -384,7 +442,8 @@ k_pair_f32_smem(const float4* __restrict__ pos, const float4* __restrict__ frc,
             pj[u] = pos[j + u];
             fj[u] = frc[j + u];
         }
-        pair_group<TENSOR, ACC, GROUP_U, ILP>(L, pj, fj, j, n, pc, gamma, m3g, thr2, x64);
+        pair_group<TENSOR, ACC, GROUP_U, ILP>(L, pj, fj, j, n, pc, gamma, m3g, thr2, x64,
+                                              near_slot, NS);
     }
     for (; j < jend; ++j) {
         const float4 pj = pos[j];
@@ -393,7 +452,7 @@ k_pair_f32_smem(const float4* __restrict__ pos, const float4* __restrict__ frc,
         for (int q = 0; q < ILP; ++q)
             pair_f32<TENSOR, ACC != 0>(L[q], pj, fj, j, n, pc, gamma, m3g, thr2, x64);
     }
-    lanes_store<ILP>(L, n, s, pc.alpha, partial);
+    lanes_store<ILP>(L, n, s, pc.alpha, near_slot, NS, partial);
 }
 
 // ---------------------------------------------------------------- FP64 path
@@ -440,7 +499,6 @@ k_pair_f64_lds(const double4* __restrict__ pos, const double4* __restrict__ frc,
             rp = pos[jn];
             rf = frc[jn];
         }
-#pragma unroll 2
         for (int k = 0; k < BLOCK; ++k) {
             const double4 pj = s_pos[k];
             const double4 fj = s_frc[k];
@@ -538,6 +596,7 @@ hipError_t launch_pair_f32(const PairLaunch& L, int tensor, int acc, const float
     case 1: return launch_f32_b<T, 1>(L, pos, frc, x64, n, pc, partial, st);         \
     case 2: return launch_f32_b<T, 2>(L, pos, frc, x64, n, pc, partial, st);         \
     case 4: return launch_f32_b<T, 4>(L, pos, frc, x64, n, pc, partial, st);         \
+    case 8: return launch_f32_b<T, 8>(L, pos, frc, x64, n, pc, partial, st);         \
     default: return hipErrorInvalidValue;                                            \
     }
     if (tensor == T_OSEEN) { SD_ACC(T_OSEEN) }

@@ -184,7 +184,7 @@ sd_kernel_config default_config(int32_t prec, int64_t n)
     c.variant = 0;
     c.block = 256;
     c.ilp = 1;
-    c.kahan_block = (prec == SD_FP32_PLAIN) ? 0 : 4;
+    c.kahan_block = (prec == SD_FP32_PLAIN) ? 0 : 8;
     if (prec == SD_FP64) {
         c.variant = 0;
         c.kahan_block = 0;
@@ -230,6 +230,8 @@ sd_status check_config(int32_t prec, const sd_kernel_config& c)
 {
     if (c.block != 64 && c.block != 128 && c.block != 256)
         return fail(SD_EINVAL, "block must be 64, 128 or 256");
+    if (c.kahan_block == 8 && c.block < 128)
+        return fail(SD_EINVAL, "kahan_block 8 needs block >= 128");
     if (c.splits < 1) return fail(SD_EINVAL, "splits must be >= 1");
     if (c.variant != 0 && c.variant != 1) return fail(SD_EINVAL, "variant must be 0 or 1");
     if (c.ilp != 1 && c.ilp != 2) return fail(SD_EINVAL, "ilp must be 1 or 2");
@@ -238,8 +240,9 @@ sd_status check_config(int32_t prec, const sd_kernel_config& c)
             return fail(SD_EINVAL, "the FP64 path has variant 0 and ilp 1 only");
     } else if (prec == SD_FP32_PLAIN) {
         if (c.kahan_block != 0) return fail(SD_EINVAL, "kahan_block must be 0 for SD_FP32_PLAIN");
-    } else if (c.kahan_block != 1 && c.kahan_block != 2 && c.kahan_block != 4) {
-        return fail(SD_EINVAL, "kahan_block must be 1, 2 or 4 for SD_FP32_KAHAN");
+    } else if (c.kahan_block != 1 && c.kahan_block != 2 && c.kahan_block != 4 &&
+               c.kahan_block != 8) {
+        return fail(SD_EINVAL, "kahan_block must be 1, 2, 4 or 8 for SD_FP32_KAHAN");
     }
     return SD_OK;
 }
