@@ -9,7 +9,9 @@
 //   grad_r [u.T.w] = alpha [ (dA'/dr (u.w) + dBt'/dr (u.r)(w.r)) rhat
 //                            + Bt' ((w.r) u + (u.r) w) ].
 // The force gradient is M(x)^T lam = M(x) lam (block symmetry of the mobility
-// matrix), i.e. the forward kernel with lam in place of F.
+// matrix): mu0 lam_i + sum_{j != i} T(r) lam_j.  The adjoint pair kernel
+// accumulates it in the same pass (lam_j . d is needed for the position
+// gradient anyway), so one kernel gives both gradients.
 #include "sd.h"
 #include "sd_host.h"
 #include "sd_internal.h"
@@ -68,10 +70,47 @@ struct LaneAdj {
     float x, y, z;       // position of i
     float lx, ly, lz;    // cotangent lam_i
     float fx, fy, fz;    // force F_i
-    float s0, s1, s2, c0, c1, c2;
-    double n0, n1, n2;
+    float s0, s1, s2, c0, c1, c2;        // position gradient (Kahan)
+    float g0, g1, g2, e0, e1, e2;        // (M lam)_i pair part (Kahan)
+    double n0, n1, n2;                   // near pairs, position gradient
+    double m0, m1, m2;                   // near pairs, M lam
     int i;
 };
+
+// FP64 T(r) lam_j of one near pair (d = x_i - x_j), the same definitions as
+// the product kernels.
+template <int TENSOR>
+__device__ __forceinline__ void adj_near_mlam(const PairConst& pc, double d0, double d1, double d2,
+                                              const double* lj, double& m0, double& m1,
+                                              double& m2)
+{
+    const double r2 = d0 * d0 + d1 * d1 + d2 * d2;
+    if (r2 == 0.0) {
+        if (TENSOR == T_RPY && pc.overlap) {
+            m0 += pc.mu0 * lj[0];
+            m1 += pc.mu0 * lj[1];
+            m2 += pc.mu0 * lj[2];
+        }
+        return;
+    }
+    const double r = sqrt(r2);
+    double cI, cD;
+    if (TENSOR == T_OSEEN) {
+        cI = pc.alpha / r;
+        cD = cI / r2;
+    } else if (pc.overlap && r < 2.0 * pc.a) {
+        cI = pc.mu0 * (1.0 - 9.0 * r / (32.0 * pc.a));
+        cD = pc.mu0 * 3.0 / (32.0 * pc.a * r);
+    } else {
+        const double ri = 1.0 / r, ri2 = ri * ri, ri3 = ri * ri2;
+        cI = pc.alpha * (ri + pc.gamma * ri3);
+        cD = pc.alpha * ri3 * (1.0 - 3.0 * pc.gamma * ri2);
+    }
+    const double dl = d0 * lj[0] + d1 * lj[1] + d2 * lj[2];
+    m0 += cI * lj[0] + cD * dl * d0;
+    m1 += cI * lj[1] + cD * dl * d1;
+    m2 += cI * lj[2] + cD * dl * d2;
+}
 
 // masked pair (handles near pairs and the self pair in FP64)
 template <int TENSOR>
@@ -98,6 +137,7 @@ __device__ __forceinline__ void adj_pair_masked(LaneAdj& L, const float4 pj, con
             const double li[3] = { L.lx, L.ly, L.lz }, fi[3] = { L.fx, L.fy, L.fz };
             const double fjd[3] = { fj.x, fj.y, fj.z }, ljd[3] = { lj.x, lj.y, lj.z };
             adj_near<TENSOR>(pc, d0, d1, d2, li, fjd, ljd, fi, L.n0, L.n1, L.n2);
+            adj_near_mlam<TENSOR>(pc, d0, d1, d2, ljd, L.m0, L.m1, L.m2);
         }
         return;
     }
@@ -134,6 +174,19 @@ __device__ __forceinline__ void adj_pair_masked(LaneAdj& L, const float4 pj, con
     L.s0 = t0;
     L.s1 = t1;
     L.s2 = t2;
+    // M lam: A lam_j + Bt (d . lam_j) d
+    const float A = (TENSOR == T_OSEEN) ? rinv : fmaf(gamma, rinv3, rinv);
+    const float sl = Bt * lj_d;
+    const float z0 = fmaf(A, lj.x, fmaf(sl, dx, -L.e0));
+    const float z1 = fmaf(A, lj.y, fmaf(sl, dy, -L.e1));
+    const float z2 = fmaf(A, lj.z, fmaf(sl, dz, -L.e2));
+    const float u0 = L.g0 + z0, u1 = L.g1 + z1, u2 = L.g2 + z2;
+    L.e0 = (u0 - L.g0) - z0;
+    L.e1 = (u1 - L.g1) - z1;
+    L.e2 = (u2 - L.g2) - z2;
+    L.g0 = u0;
+    L.g1 = u1;
+    L.g2 = u2;
 }
 
 // LDS-tiled adjoint pair kernel: tiles of BLOCK j-particles (position, force,
@@ -143,7 +196,7 @@ template <int TENSOR, int BLOCK>
 __global__ void __launch_bounds__(BLOCK)
 k_adjoint_f32(const float4* __restrict__ pos, const float4* __restrict__ frc,
               const float4* __restrict__ lam, const double* __restrict__ x64, int n, int jchunk,
-              PairConst pc, double* __restrict__ partial)
+              PairConst pc, double* __restrict__ partial, double* __restrict__ partial_f)
 {
     __shared__ float4 s_pos[BLOCK];
     __shared__ float4 s_frc[BLOCK];
@@ -164,7 +217,9 @@ k_adjoint_f32(const float4* __restrict__ pos, const float4* __restrict__ frc,
         L.fx = f.x; L.fy = f.y; L.fz = f.z;
         L.lx = l.x; L.ly = l.y; L.lz = l.z;
         L.s0 = L.s1 = L.s2 = L.c0 = L.c1 = L.c2 = 0.0f;
+        L.g0 = L.g1 = L.g2 = L.e0 = L.e1 = L.e2 = 0.0f;
         L.n0 = L.n1 = L.n2 = 0.0;
+        L.m0 = L.m1 = L.m2 = 0.0;
     }
     const float gamma = pc.gamma_f, thr2 = pc.thr2_f;
     const float g3 = -3.0f * gamma, m3g = 3.0f * gamma, g15 = 15.0f * gamma;
@@ -215,6 +270,7 @@ k_adjoint_f32(const float4* __restrict__ pos, const float4* __restrict__ frc,
                 continue;
             }
             float y0 = -L.c0, y1 = -L.c1, y2 = -L.c2;
+            float z0 = -L.e0, z1 = -L.e1, z2 = -L.e2;
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
                 const float rinv = __builtin_amdgcn_rsqf(r2[u]);
@@ -242,6 +298,12 @@ k_adjoint_f32(const float4* __restrict__ pos, const float4* __restrict__ frc,
                 y0 = fmaf(c1, dx[u], fmaf(Bt, w0, y0));
                 y1 = fmaf(c1, dy[u], fmaf(Bt, w1, y1));
                 y2 = fmaf(c1, dz[u], fmaf(Bt, w2, y2));
+                // M lam
+                const float A = (TENSOR == T_OSEEN) ? rinv : fmaf(gamma, rinv3, rinv);
+                const float sl = Bt * lj_d;
+                z0 = fmaf(A, lj[u].x, fmaf(sl, dx[u], z0));
+                z1 = fmaf(A, lj[u].y, fmaf(sl, dy[u], z1));
+                z2 = fmaf(A, lj[u].z, fmaf(sl, dz[u], z2));
             }
             const float t0 = L.s0 + y0, t1 = L.s1 + y1, t2 = L.s2 + y2;
             L.c0 = (t0 - L.s0) - y0;
@@ -250,6 +312,13 @@ k_adjoint_f32(const float4* __restrict__ pos, const float4* __restrict__ frc,
             L.s0 = t0;
             L.s1 = t1;
             L.s2 = t2;
+            const float u0 = L.g0 + z0, u1 = L.g1 + z1, u2 = L.g2 + z2;
+            L.e0 = (u0 - L.g0) - z0;
+            L.e1 = (u1 - L.g1) - z1;
+            L.e2 = (u2 - L.g2) - z2;
+            L.g0 = u0;
+            L.g1 = u1;
+            L.g2 = u2;
         }
     }
     if (L.i < n) {
@@ -257,6 +326,9 @@ k_adjoint_f32(const float4* __restrict__ pos, const float4* __restrict__ frc,
         partial[base] = pc.alpha * ((double)L.s0 - (double)L.c0) + L.n0;
         partial[base + (size_t)n] = pc.alpha * ((double)L.s1 - (double)L.c1) + L.n1;
         partial[base + 2 * (size_t)n] = pc.alpha * ((double)L.s2 - (double)L.c2) + L.n2;
+        partial_f[base] = pc.alpha * ((double)L.g0 - (double)L.e0) + L.m0;
+        partial_f[base + (size_t)n] = pc.alpha * ((double)L.g1 - (double)L.e1) + L.m1;
+        partial_f[base + 2 * (size_t)n] = pc.alpha * ((double)L.g2 - (double)L.e2) + L.m2;
     }
 }
 
@@ -264,7 +336,7 @@ template <int TENSOR, int BLOCK>
 __global__ void __launch_bounds__(BLOCK)
 k_adjoint_f64(const double4* __restrict__ pos, const double4* __restrict__ frc,
               const double4* __restrict__ lam, int n, int jchunk, PairConst pc,
-              double* __restrict__ partial)
+              double* __restrict__ partial, double* __restrict__ partial_f)
 {
     __shared__ double4 s_pos[BLOCK];
     __shared__ double4 s_frc[BLOCK];
@@ -280,6 +352,7 @@ k_adjoint_f64(const double4* __restrict__ pos, const double4* __restrict__ frc,
         li[0] = l.x; li[1] = l.y; li[2] = l.z;
     }
     double g0 = 0.0, g1 = 0.0, g2 = 0.0;
+    double m0 = 0.0, m1 = 0.0, m2 = 0.0;
     const int jbeg = s * jchunk;
     const int jend = min(n, jbeg + jchunk);
     const double4 far_j = make_double4(1.0e15, 1.0e15, 1.0e15, 0.0);
@@ -312,6 +385,7 @@ k_adjoint_f64(const double4* __restrict__ pos, const double4* __restrict__ frc,
             const double fj[3] = { fj4.x, fj4.y, fj4.z }, lj[3] = { lj4.x, lj4.y, lj4.z };
             adj_near<TENSOR>(pc, xi[0] - pj.x, xi[1] - pj.y, xi[2] - pj.z, li, fj, lj, fi, g0, g1,
                              g2);
+            adj_near_mlam<TENSOR>(pc, xi[0] - pj.x, xi[1] - pj.y, xi[2] - pj.z, lj, m0, m1, m2);
         }
     }
     if (i < n) {
@@ -319,36 +393,80 @@ k_adjoint_f64(const double4* __restrict__ pos, const double4* __restrict__ frc,
         partial[base] = g0;
         partial[base + (size_t)n] = g1;
         partial[base + 2 * (size_t)n] = g2;
+        partial_f[base] = m0;
+        partial_f[base + (size_t)n] = m1;
+        partial_f[base + 2 * (size_t)n] = m2;
+    }
+}
+
+// Merge of the adjoint partials (fixed split order):
+//   single product (lam64 == null): gpos = sum P;  gforce = mu0 lam4 + sum F
+//   Euler loop (lam64 != null):     gforce += dt (mu0 lam_old + sum F);
+//                                   lam64 = lam_old + dt sum P   (gpos unused)
+template <typename P4>
+__global__ void __launch_bounds__(256)
+k_adjoint_merge(const double* __restrict__ pp, const double* __restrict__ pf, int S, int n,
+                const P4* __restrict__ lam4, double* __restrict__ lam64, double mu0, double dt,
+                double* __restrict__ gpos, double* __restrict__ gforce)
+{
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    double a[3] = { 0.0, 0.0, 0.0 }, b[3] = { 0.0, 0.0, 0.0 };
+    for (int s = 0; s < S; ++s) {
+        const size_t base = (size_t)s * 3 * (size_t)n + (size_t)i;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            a[k] += pp[base + (size_t)k * n];
+            b[k] += pf[base + (size_t)k * n];
+        }
+    }
+    if (lam64) {
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const size_t e = 3 * (size_t)i + k;
+            const double lo = lam64[e];
+            gforce[e] += dt * (mu0 * lo + b[k]);
+            lam64[e] = lo + dt * a[k];
+        }
+    } else {
+        const P4 l = lam4[i];
+        const double lv[3] = { (double)l.x, (double)l.y, (double)l.z };
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const size_t e = 3 * (size_t)i + k;
+            if (gpos) gpos[e] = a[k];
+            if (gforce) gforce[e] = mu0 * lv[k] + b[k];
+        }
     }
 }
 
 hipError_t launch_adjoint_f32(const PairLaunch& L, int tensor, const float4* pos, const float4* frc,
                               const float4* lam, const double* x64, int n, const PairConst& pc,
-                              double* partial, hipStream_t st)
+                              double* partial, double* partial_f, hipStream_t st)
 {
     if (L.block != 256) return hipErrorInvalidValue;
     dim3 grid((n + 255) / 256, L.splits), block(256);
     if (tensor == T_OSEEN)
         hipLaunchKernelGGL((k_adjoint_f32<T_OSEEN, 256>), grid, block, 0, st, pos, frc, lam, x64,
-                           n, L.jchunk, pc, partial);
+                           n, L.jchunk, pc, partial, partial_f);
     else
         hipLaunchKernelGGL((k_adjoint_f32<T_RPY, 256>), grid, block, 0, st, pos, frc, lam, x64, n,
-                           L.jchunk, pc, partial);
+                           L.jchunk, pc, partial, partial_f);
     return hipGetLastError();
 }
 
 hipError_t launch_adjoint_f64(const PairLaunch& L, int tensor, const double4* pos,
                               const double4* frc, const double4* lam, int n, const PairConst& pc,
-                              double* partial, hipStream_t st)
+                              double* partial, double* partial_f, hipStream_t st)
 {
     if (L.block != 256) return hipErrorInvalidValue;
     dim3 grid((n + 255) / 256, L.splits), block(256);
     if (tensor == T_OSEEN)
         hipLaunchKernelGGL((k_adjoint_f64<T_OSEEN, 256>), grid, block, 0, st, pos, frc, lam, n,
-                           L.jchunk, pc, partial);
+                           L.jchunk, pc, partial, partial_f);
     else
         hipLaunchKernelGGL((k_adjoint_f64<T_RPY, 256>), grid, block, 0, st, pos, frc, lam, n,
-                           L.jchunk, pc, partial);
+                           L.jchunk, pc, partial, partial_f);
     return hipGetLastError();
 }
 
@@ -362,25 +480,38 @@ static PairLaunch plan_adjoint(int32_t prec, int64_t n)
     return L;
 }
 
-// grad_pos[3n] = sum over splits of the adjoint partials (scaled, optionally accumulated)
-static sd_status adjoint_into(const sd_params* p, int64_t n, const void* pos, const void* frc,
-                              const void* lam, const double* x64, int32_t prec, double* out,
-                              double scale, int accumulate, hipStream_t hs)
+// One adjoint pass: the fused pair kernel, then the merge (see k_adjoint_merge).
+static sd_status adjoint_pass(const sd_params* p, int64_t n, const void* pos, const void* frc,
+                              const void* lam4, const double* x64, int32_t prec, double* lam64,
+                              double dt, double* gpos, double* gforce, hipStream_t hs)
 {
     sd_status st;
     const PairLaunch L = plan_adjoint(prec, n);
     void* partial = nullptr;
-    if ((st = ws_get(WS_ADJ_PARTIAL, partial_bytes(L, n), &partial))) return st;
+    const size_t pb = partial_bytes(L, n);
+    if ((st = ws_get(WS_ADJ_PARTIAL, 2 * pb, &partial))) return st;
+    double* pp = (double*)partial;
+    double* pf = (double*)((char*)partial + pb);
     const PairConst pc = pair_const(p);
-    hipError_t e = (prec == SD_FP64)
-                       ? launch_adjoint_f64(L, p->tensor, (const double4*)pos, (const double4*)frc,
-                                            (const double4*)lam, (int)n, pc, (double*)partial, hs)
-                       : launch_adjoint_f32(L, p->tensor, (const float4*)pos, (const float4*)frc,
-                                            (const float4*)lam, x64, (int)n, pc, (double*)partial,
-                                            hs);
-    if (e != hipSuccess) return fail(SD_EDEVICE, "adjoint kernel launch: %s", hipGetErrorString(e));
-    e = launch_sum_partials((double*)partial, L.splits, (int)n, out, scale, accumulate, hs);
-    if (e != hipSuccess) return fail(SD_EDEVICE, "adjoint merge launch: %s", hipGetErrorString(e));
+    const double mu0 = 1.0 / (6.0 * M_PI * p->eta * p->a);
+    hipError_t e;
+    if (prec == SD_FP64) {
+        e = launch_adjoint_f64(L, p->tensor, (const double4*)pos, (const double4*)frc,
+                               (const double4*)lam4, (int)n, pc, pp, pf, hs);
+        if (e == hipSuccess)
+            hipLaunchKernelGGL((k_adjoint_merge<double4>), dim3((unsigned)((n + 255) / 256)),
+                               dim3(256), 0, hs, pp, pf, L.splits, (int)n, (const double4*)lam4,
+                               lam64, mu0, dt, gpos, gforce);
+    } else {
+        e = launch_adjoint_f32(L, p->tensor, (const float4*)pos, (const float4*)frc,
+                               (const float4*)lam4, x64, (int)n, pc, pp, pf, hs);
+        if (e == hipSuccess)
+            hipLaunchKernelGGL((k_adjoint_merge<float4>), dim3((unsigned)((n + 255) / 256)),
+                               dim3(256), 0, hs, pp, pf, L.splits, (int)n, (const float4*)lam4,
+                               lam64, mu0, dt, gpos, gforce);
+    }
+    if (e == hipSuccess) e = hipGetLastError();
+    if (e != hipSuccess) return fail(SD_EDEVICE, "adjoint launch: %s", hipGetErrorString(e));
     return SD_OK;
 }
 
@@ -402,11 +533,8 @@ sd_status mobility_adjoint(const sd_params* p, int64_t n, const void* pos, const
         return st;
     if (grad_force && (uintptr_t)grad_force % 8)
         return fail(SD_EALIGN, "grad_force is not 8-byte aligned");
-    hipStream_t hs = (hipStream_t)stream;
-    if ((st = adjoint_into(p, n, pos, force, lam, nullptr, precision, grad_pos, 1.0, 0, hs)))
-        return st;
-    if (grad_force) return mobility_apply(p, n, pos, lam, grad_force, precision, stream);
-    return SD_OK;
+    return adjoint_pass(p, n, pos, force, lam, nullptr, precision, nullptr, 0.0, grad_pos,
+                        grad_force, (hipStream_t)stream);
 }
 
 sd_status sd_run_adjoint(const sd_params* p, int64_t n, const double* x0, const void* force,
@@ -458,12 +586,11 @@ sd_status sd_run_adjoint(const sd_params* p, int64_t n, const double* x0, const 
         }
         ck = xw;
     }
-    void *traj = nullptr, *pos = nullptr, *lam4 = nullptr, *tmp = nullptr;
+    void *traj = nullptr, *pos = nullptr, *lam4 = nullptr;
     if ((st = ws_get(WS_ADJ_TRAJ, frame * (size_t)E, &traj)) ||
         (st = ws_get(WS_STAGE, rec * (size_t)n, &pos)) ||
-        (st = ws_get(WS_ADJ_PACK, rec * (size_t)n + frame, &lam4)))
+        (st = ws_get(WS_ADJ_PACK, rec * (size_t)n, &lam4)))
         return st;
-    tmp = (char*)lam4 + rec * (size_t)n;  // f64[3n] scratch after the packed cotangent
     // lam lives in grad_x0 (initialised with grad_xN above)
     double* lam = grad_x0;
     double* T = (double*)traj;
@@ -494,13 +621,9 @@ sd_status sd_run_adjoint(const sd_params* p, int64_t n, const double* x0, const 
                 e = f64 ? launch_pack_f64(lam, (double4*)lam4, (int)n, hs)
                         : launch_pack_f32(lam, (float4*)lam4, (int)n, hs);
             if (e != hipSuccess) return fail(SD_EDEVICE, "pack launch: %s", hipGetErrorString(e));
-            // dL/dF += dt M(x_k) lam_{k+1}
-            if ((st = mobility_apply(p, n, pos, lam4, (double*)tmp, precision, stream))) return st;
-            if ((e = launch_axpy(dt, (double*)tmp, grad_force, (int64_t)m, hs)) != hipSuccess)
-                return fail(SD_EDEVICE, "axpy launch: %s", hipGetErrorString(e));
-            // lam_k = lam_{k+1} + dt d/dx [lam_{k+1} . M(x_k) F]
-            if ((st = adjoint_into(p, n, pos, force, lam4, f64 ? nullptr : xk, precision, lam, dt,
-                                   1, hs)))
+            // dL/dF += dt M(x_k) lam_{k+1};  lam_k = lam_{k+1} + dt d/dx [lam_{k+1} . M(x_k) F]
+            if ((st = adjoint_pass(p, n, pos, force, lam4, f64 ? nullptr : xk, precision, lam, dt,
+                                   nullptr, grad_force, hs)))
                 return st;
         }
     }

@@ -77,13 +77,14 @@ hipError_t launch_merge_integrate_f64(const double* partial, int splits, int n, 
                                       double mu0, double* x, double* v_prev, double* v_out,
                                       double dt, int mode, double4* pos_next, hipStream_t st);
 
-// Adjoint pair kernels: partial[(s*3+k)*n + i] = position gradient terms.
+// Adjoint pair kernels: partial[(s*3+k)*n + i] = position gradient terms,
+// partial_f[...] = pair part of (M lam)_i.
 hipError_t launch_adjoint_f32(const PairLaunch& L, int tensor, const float4* pos, const float4* frc,
                               const float4* lam, const double* x64, int n, const PairConst& pc,
-                              double* partial, hipStream_t st);
+                              double* partial, double* partial_f, hipStream_t st);
 hipError_t launch_adjoint_f64(const PairLaunch& L, int tensor, const double4* pos,
                               const double4* frc, const double4* lam, int n, const PairConst& pc,
-                              double* partial, hipStream_t st);
+                              double* partial, double* partial_f, hipStream_t st);
 // out[3i+k] = sum_s partial (no self term); accumulate != 0 adds scale*sum to out.
 hipError_t launch_sum_partials(const double* partial, int splits, int n, double* out, double scale,
                                int accumulate, hipStream_t st);

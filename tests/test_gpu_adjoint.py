@@ -143,3 +143,40 @@ def test_autograd_mobility_and_run(sd, orc):
     loss.backward()
     assert rel2(x0t.grad.cpu().numpy(), gx_ref) <= 1e-10
     assert rel2(F0t.grad.cpu().numpy(), gf_ref) <= 1e-10
+
+
+def test_adjoint_full_size_directional_fd(sd):
+    """The N = 8192, 200-step differentiation workload (checkpoint every 20)
+    in FP64: the adjoint gradient's projection on random directions of x0 and
+    F equals the central difference of the loss computed with the forward
+    pass.  A property that holds at any size (the oracle adjoint is too slow
+    here)."""
+    import torch
+    n, steps, dt = 8192, 200, 0.01
+    x0, F0, Fp, _, _ = _diff_case(n, steps, dt, seed=1)
+    frc = to_dev4(F0, torch.float64)
+    xt = to_dev3(x0)
+    sd.sd_run(xt, to_dev4(Fp, torch.float64), dt, steps, precision=sd.SD_FP64)
+
+    def loss(xa, Fa):
+        xe = to_dev3(xa)
+        sd.sd_run(xe, to_dev4(Fa, torch.float64), dt, steps, precision=sd.SD_FP64)
+        return float(((xe - xt) ** 2).sum())
+
+    xe = to_dev3(x0)
+    sd.sd_run(xe, frc, dt, steps, precision=sd.SD_FP64)
+    gx, gf = sd.sd_run_adjoint(to_dev3(x0), frc, dt, steps, (2 * (xe - xt)).contiguous(),
+                               checkpoint_every=20, precision=sd.SD_FP64)
+    gx, gf = gx.cpu().numpy(), gf.cpu().numpy()
+    rng = np.random.default_rng(11)
+    for which in ("x", "F"):
+        d = rng.standard_normal((n, 3))
+        h = 1e-5
+
+        def L(t):
+            return loss(x0 + t * d, F0) if which == "x" else loss(x0, F0 + t * d)
+        # fourth-order central difference (truncation O(h^4))
+        fd = (8 * (L(h) - L(-h)) - (L(2 * h) - L(-2 * h))) / (12 * h)
+        an = float(((gx if which == "x" else gf) * d).sum())
+        print("%s: adjoint %.10e fd %.10e rel %.2e" % (which, an, fd, abs(an - fd) / abs(fd)))
+        assert abs(an - fd) <= 1e-7 * abs(fd)

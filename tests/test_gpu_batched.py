@@ -157,3 +157,29 @@ def test_autotune_installs_a_valid_config(sd, orc):
     v = sd.mobility_apply(to_dev4(xo, torch.float32), to_dev4(fo, torch.float32))
     torch.cuda.synchronize()
     assert rel2(v.cpu().numpy(), orc.mobility(orc.params(), xo, fo)) <= 1e-6, cfg
+
+
+def test_batched_full_workload_sampled_clusters(sd, orc):
+    """The 4096-cluster workload (N_c ~ U{4..256}, 100 Euler steps, dt = 0.01,
+    graph launch) in its launch configuration; 48 sampled clusters (plus the
+    largest and the smallest) against independent oracle runs."""
+    import torch
+    offsets, x = W.clusters(4096, nmin=4, nmax=256, sigma=4.0, seed=3)
+    f = W.gravity_forces(len(x))
+    b = sd.Batch(offsets)
+    xd = to_dev3(x)
+    sd.sd_run_batched(b, xd, to_dev4(f, torch.float32), 0.01, 100, use_graph=True)
+    torch.cuda.synchronize()
+    xg = xd.cpu().numpy()
+    sizes = np.diff(offsets)
+    pick = np.unique(np.concatenate([[int(np.argmax(sizes)), int(np.argmin(sizes))],
+                                     np.random.default_rng(8).choice(4096, 48, replace=False)]))
+    p = orc.params()
+    worst = 0.0
+    for c in pick:
+        a, e = offsets[c], offsets[c + 1]
+        ref, _, _ = orc.run(p, x[a:e], f[a:e], 0.01, 100)
+        worst = max(worst, np.abs(xg[a:e] - ref).max() / np.abs(ref - x[a:e]).max())
+    print("worst err/disp over %d clusters: %.3e" % (len(pick), worst))
+    assert worst <= 1e-6
+    b.close()

@@ -115,3 +115,32 @@ def test_checkpoints_and_v_out(sd, orc):
     sd.sd_step(xe, _force(sd, f, 1), 0.02, 0, v_out=vo, precision=sd.SD_FP64)
     torch.cuda.synchronize()
     np.testing.assert_allclose(vo.cpu().numpy(), orc.mobility(orc.params(), x0, f), rtol=1e-12)
+
+
+def test_sedimentation_full_size_two_steps(sd, orc):
+    """The N = 65536 sedimentation workload (overlap RPY, AB2 dt = 0.005) in the
+    automatic launch configuration: two steps against a full oracle run (the
+    second AB2 step depends on every particle), compared on 2048 sampled rows
+    and in the centre-of-mass velocity."""
+    import torch
+    n = 65536
+    x0 = W.random_suspension(n, phi=0.05, seed=1)
+    f = W.gravity_forces(n)
+    p = sd.params(overlap=True)
+    po = orc.params(overlap=True)
+    xr, vr, _ = orc.run(po, x0, f, 0.005, 2, orc.AB2)
+    rows = np.unique(np.concatenate([[0, n - 1],
+                                     np.random.default_rng(5).choice(n, 2046, replace=False)]))
+    disp = np.abs(xr - x0)[rows].max()
+    for prec, tol in ((sd.SD_FP32_KAHAN, 1e-6), (sd.SD_FP64, 1e-12)):
+        xd = to_dev3(x0)
+        vp = torch.zeros_like(xd)
+        sd.sd_run(xd, _force(sd, f, prec), 0.005, 2, v_prev=vp, integrator=sd.SD_AB2, params=p,
+                  precision=prec)
+        vcm = sd.sd_mean_vector(vp)
+        torch.cuda.synchronize()
+        xg = xd.cpu().numpy()
+        err = np.abs(xg[rows] - xr[rows]).max() / disp
+        print("prec=%d 2-step err/disp=%.3e" % (prec, err))
+        assert err <= tol
+        np.testing.assert_allclose(vcm.cpu().numpy(), vr.mean(0), rtol=10 * tol)
