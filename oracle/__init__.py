@@ -29,6 +29,10 @@ class OracleParams(ctypes.Structure):
                 ("tensor", ctypes.c_int), ("overlap", ctypes.c_int)]
 
 
+class OracleLub(ctypes.Structure):
+    _fields_ = [("s_cut", ctypes.c_double), ("s_min", ctypes.c_double)]
+
+
 def build(force: bool = True) -> str:
     """Compile sd_oracle.c into liboracle.so (gcc -O2, no fast-math, OpenMP)."""
     if force or not os.path.exists(_LIB):
@@ -64,6 +68,12 @@ def _load():
         lib.oracle_run_adjoint_euler.restype = ctypes.c_int
         lib.oracle_threads.argtypes = []
         lib.oracle_threads.restype = ctypes.c_int
+        LP = ctypes.POINTER(OracleLub)
+        lib.oracle_lub_tensor.argtypes = [P, LP, d, d]
+        lib.oracle_lubrication_force.argtypes = [P, LP, i64, d, d, d]
+        lib.oracle_run_lub.argtypes = [P, LP, i64, d, d, ctypes.c_double, i64, i64, ctypes.c_int,
+                                       d, d, i64]
+        lib.oracle_run_lub.restype = ctypes.c_int
         _lib = lib
     return _lib
 
@@ -189,3 +199,42 @@ def run_adjoint_euler(p: OracleParams, x0, f, dt: float, steps: int, lam_final):
     if rc != 0:
         raise MemoryError("oracle_run_adjoint_euler failed")
     return gx, gf
+
+
+def lub(s_cut: float = 1.0, s_min: float = 1e-3) -> OracleLub:
+    """Lubrication truncation (Sec. 2.3: s < 1) and the contact clamp s >= s_min."""
+    return OracleLub(float(s_cut), float(s_min))
+
+
+def lub_tensor(p: OracleParams, lb: OracleLub, r) -> np.ndarray:
+    """3x3 singular friction zeta(r) of Eq. 8 (physical units)."""
+    r = np.ascontiguousarray(np.asarray(r, dtype=np.float64).reshape(3))
+    Z = np.empty(9)
+    _load().oracle_lub_tensor(ctypes.byref(p), ctypes.byref(lb), _ptr(r), _ptr(Z))
+    return Z.reshape(3, 3)
+
+
+def lubrication_force(p: OracleParams, lb: OracleLub, x, v) -> np.ndarray:
+    """f_i = - sum_j zeta(r_i - r_j) (v_i - v_j)."""
+    x = _vec(x)
+    v = _vec(v, x.shape[0])
+    f = np.empty_like(x)
+    _load().oracle_lubrication_force(ctypes.byref(p), ctypes.byref(lb), x.shape[0], _ptr(x),
+                                     _ptr(v), _ptr(f))
+    return f
+
+
+def run_lub(p: OracleParams, lb: OracleLub, x0, f_ext, dt: float, steps: int,
+            integrator: int = EULER, step0: int = 0, v_prev=None, stride: int = 0):
+    """The loop of Sec. 3.1 with lubrication; returns (x, v_last, traj or None)."""
+    x = _vec(x0).copy()
+    n = x.shape[0]
+    f = _vec(f_ext, n)
+    vp = np.zeros_like(x) if v_prev is None else _vec(v_prev, n).copy()
+    traj = np.empty((steps // stride + 1, n, 3)) if stride > 0 else None
+    rc = _load().oracle_run_lub(ctypes.byref(p), ctypes.byref(lb), n, _ptr(x), _ptr(f), float(dt),
+                                int(steps), int(step0), int(integrator), _ptr(vp), _ptr(traj),
+                                int(stride))
+    if rc != 0:
+        raise MemoryError("oracle_run_lub failed")
+    return x, vp, traj

@@ -24,7 +24,11 @@
  *   - AB2 integrator (the paper only suggests higher-order schemes), first
  *     step explicit Euler;
  *   - the velocity at step n is computed from the positions at step n before
- *     the positions move (standard explicit Euler).
+ *     the positions move (standard explicit Euler);
+ *   - lubrication (Eq. 8): the surface separation s = r/a - 2 is clamped below
+ *     at s_min (the paper does not say what happens at contact or overlap),
+ *     and the previous step's velocities are supplied by the caller (zero or
+ *     any other initial guess before the first step).
  */
 #include <math.h>
 #ifdef _OPENMP
@@ -324,5 +328,102 @@ int oracle_run_adjoint_euler(const oracle_params* p, int64_t n, const double* x0
     }
     memcpy(grad_x0, lam, sizeof(double) * m);
     free(xs); free(lam); free(tmp); free(v);
+    return 0;
+}
+
+/* ------------------------------------------------------------ lubrication */
+
+typedef struct {
+    double s_cut;   /* truncation: pairs with s = r/a - 2 < s_cut (Sec. 2.3: s_cut = 1) */
+    double s_min;   /* s is clamped to >= s_min (reading: contact / overlap) */
+} oracle_lub;
+
+/*
+ * Singular lubrication friction of one pair, Eq. (8), Sec. 2.3:
+ *   mu0 zeta(r) = [1/(4s) - 9/40 log s] rhat rhat - 1/6 log s (I - rhat rhat),
+ *   s = r/a - 2, for s < s_cut; zero otherwise.  3x3 row-major, physical units.
+ */
+void oracle_lub_tensor(const oracle_params* p, const oracle_lub* lub, const double r[3],
+                       double Z[9])
+{
+    const double mu0 = stokes_mobility(p);
+    const double rr = sqrt(r[0] * r[0] + r[1] * r[1] + r[2] * r[2]);
+    for (int k = 0; k < 9; ++k) Z[k] = 0.0;
+    if (rr == 0.0) return;
+    double s = rr / p->a - 2.0;
+    if (s >= lub->s_cut) return;
+    if (s < lub->s_min) s = lub->s_min;
+    const double ls = log(s);
+    const double cP = (1.0 / (4.0 * s) - 9.0 / 40.0 * ls) / mu0;  /* rhat rhat part */
+    const double cT = (-1.0 / 6.0 * ls) / mu0;                   /* (I - rhat rhat) part */
+    const double h[3] = { r[0] / rr, r[1] / rr, r[2] / rr };
+    for (int al = 0; al < 3; ++al)
+        for (int be = 0; be < 3; ++be) {
+            const double P = h[al] * h[be];
+            Z[3 * al + be] = cP * P + cT * ((al == be ? 1.0 : 0.0) - P);
+        }
+}
+
+/*
+ * Lubrication forces of step 2 of the algorithm of Sec. 3.1:
+ *   f_i = - sum_{j != i} zeta(r_i - r_j) (v_i - v_j)
+ * over all pairs (plain double loop; the primed sum of the paper runs over the
+ * close pairs, which are exactly the pairs with a non-zero zeta).
+ */
+void oracle_lubrication_force(const oracle_params* p, const oracle_lub* lub, int64_t n,
+                              const double* x, const double* v, double* f)
+{
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t i = 0; i < n; ++i) {
+        double acc[3] = { 0.0, 0.0, 0.0 };
+        for (int64_t j = 0; j < n; ++j) {
+            if (j == i) continue;
+            const double r[3] = { x[3 * i] - x[3 * j], x[3 * i + 1] - x[3 * j + 1],
+                                  x[3 * i + 2] - x[3 * j + 2] };
+            double Z[9];
+            oracle_lub_tensor(p, lub, r, Z);
+            const double dv[3] = { v[3 * i] - v[3 * j], v[3 * i + 1] - v[3 * j + 1],
+                                   v[3 * i + 2] - v[3 * j + 2] };
+            for (int al = 0; al < 3; ++al)
+                acc[al] -= Z[3 * al] * dv[0] + Z[3 * al + 1] * dv[1] + Z[3 * al + 2] * dv[2];
+        }
+        f[3 * i] = acc[0];
+        f[3 * i + 1] = acc[1];
+        f[3 * i + 2] = acc[2];
+    }
+}
+
+/*
+ * The three-step loop of Sec. 3.1 with lubrication: at every step
+ *   F_k = F_ext - sum' zeta(x_k) (v_i - v_j) with the previous velocities v_{k-1},
+ *   v_k = M(x_k) F_k,  x_{k+1} = x_k + dt v_k  (Euler; AB2 as oracle_run).
+ * v_prev: in = the velocities before the first step, out = v of the last step.
+ * traj as in oracle_run.
+ */
+int oracle_run_lub(const oracle_params* p, const oracle_lub* lub, int64_t n, double* x,
+                   const double* f_ext, double dt, int64_t steps, int64_t step0, int integrator,
+                   double* v_prev, double* traj, int64_t stride)
+{
+    const size_t m = 3 * (size_t)n;
+    double* v = (double*)malloc(sizeof(double) * m);
+    double* F = (double*)malloc(sizeof(double) * m);
+    if (!v || !F) { free(v); free(F); return 1; }
+    int64_t frame = 0;
+    if (traj) memcpy(traj + m * frame++, x, sizeof(double) * m);
+    for (int64_t s = 0; s < steps; ++s) {
+        oracle_lubrication_force(p, lub, n, x, v_prev, F);
+        for (size_t k = 0; k < m; ++k) F[k] += f_ext[k];
+        oracle_mobility(p, n, x, F, v);
+        const int euler = (integrator == 0) || (step0 + s == 0);
+        for (size_t k = 0; k < m; ++k) {
+            if (euler) x[k] = x[k] + dt * v[k];
+            else x[k] = x[k] + dt * (1.5 * v[k] - 0.5 * v_prev[k]);
+        }
+        memcpy(v_prev, v, sizeof(double) * m);
+        if (traj && stride > 0 && (s + 1) % stride == 0)
+            memcpy(traj + m * frame++, x, sizeof(double) * m);
+    }
+    free(v);
+    free(F);
     return 0;
 }
