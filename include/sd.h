@@ -166,6 +166,41 @@ sd_status sd_run_adjoint(const sd_params* p, int64_t n, const double* x0, const 
                          int64_t checkpoint_every, const double* grad_xN, double* grad_x0,
                          double* grad_force, void* stream);
 
+/* -------------------------------------------------------------- lubrication */
+
+/* Truncation of the lubrication correction (Sec. 2.3). */
+typedef struct sd_lub {
+    double s_cut;         /* pairs with s = r/a - 2 < s_cut get the correction (paper: 1) */
+    double s_min;         /* s is clamped to >= s_min at contact or overlap (not in
+                             the paper); 0 < s_min < s_cut */
+} sd_lub;
+
+/*
+ * lubrication_forces -- step 2 of the algorithm of Sec. 3.1 with external
+ * forces and the singular lubrication friction of Eq. (8):
+ *   f_out_i = f_ext_i - sum_{j: s_ij < s_cut} zeta(r_i - r_j) (v_i - v_j),
+ *   mu0 zeta(r) = [1/(4s) - 9/40 log s] rhat rhat - 1/6 log s (I - rhat rhat).
+ *   x, v, f_out  f64[3n]; f_ext f64[3n] or NULL (zero).  FP64 throughout.
+ * Close pairs are found with a cell list rebuilt on the device (no host
+ * round trip); the result is deterministic.
+ */
+sd_status lubrication_forces(const sd_params* p, const sd_lub* lub, int64_t n, const double* x,
+                             const double* v, const double* f_ext, double* f_out, void* stream);
+
+/*
+ * sd_run_lub -- `steps` steps of the three-step loop of Sec. 3.1 with
+ * lubrication: F_k = lubrication_forces(x_k, v_{k-1}, f_ext); v_k = M(x_k) F_k;
+ * x_{k+1} = x_k + dt v_k (Euler) or AB2 (step index 0 is Euler).
+ *   f_ext   f64[3n] external forces (constant)
+ *   v_prev  f64[3n], in: velocities before the first step (the paper uses the
+ *           previous step's; zero switches the correction off for the first
+ *           step), out: velocities of the last step
+ *   other arguments as sd_run.
+ */
+sd_status sd_run_lub(const sd_params* p, const sd_lub* lub, int64_t n, double* x,
+                     const double* f_ext, double* v_prev, double dt, int64_t steps, int64_t step0,
+                     int32_t integrator, int32_t precision, void* stream);
+
 /* ------------------------------------------------------------------ batched */
 
 /* Many independent clusters: particles of different clusters do not interact

@@ -30,6 +30,15 @@ class SdParams(ctypes.Structure):
                 ("tensor", ctypes.c_int32), ("overlap", ctypes.c_int32)]
 
 
+class SdLub(ctypes.Structure):
+    _fields_ = [("s_cut", ctypes.c_double), ("s_min", ctypes.c_double)]
+
+
+def lub(s_cut: float = 1.0, s_min: float = 1e-3) -> SdLub:
+    """Lubrication truncation (paper: s < 1) and contact clamp."""
+    return SdLub(float(s_cut), float(s_min))
+
+
 class SdKernelConfig(ctypes.Structure):
     _fields_ = [("variant", ctypes.c_int32), ("block", ctypes.c_int32),
                 ("splits", ctypes.c_int32), ("ilp", ctypes.c_int32),
@@ -75,6 +84,8 @@ def lib() -> ctypes.CDLL:
             "sd_get_kernel_config": [i32, i64, ctypes.POINTER(SdKernelConfig)],
             "sd_autotune": [P, i64, i32, vp, ctypes.c_char_p, i64],
             "sd_pack": [i64, dp, vp, i32, vp],
+            "lubrication_forces": [P, ctypes.POINTER(SdLub), i64, dp, dp, dp, dp, vp],
+            "sd_run_lub": [P, ctypes.POINTER(SdLub), i64, dp, dp, dp, d, i64, i64, i32, i32, vp],
             "sd_mean_vector": [i64, dp, dp, vp],
             "sd_profile_enable": [i32],
             "sd_profile_read": [ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double)],
@@ -242,6 +253,40 @@ def sd_run_adjoint(x0, force, dt: float, steps: int, grad_xN, *, checkpoints=Non
                                prec, _ptr(checkpoints), int(checkpoint_every), _ptr(grad_xN),
                                _ptr(grad_x0), _ptr(grad_force), _stream(stream)))
     return grad_x0, grad_force
+
+
+def lubrication_forces(x, v, f_ext=None, f_out=None, *, params: SdParams = None,
+                       lub_params: SdLub = None, stream=None):
+    """f_ext - sum' zeta (v_i - v_j) for (n, 3) float64 CUDA tensors."""
+    import torch
+    n = x.shape[0]
+    _vec3(x, n, "x")
+    _vec3(v, n, "v")
+    if f_ext is not None:
+        _vec3(f_ext, n, "f_ext")
+    if f_out is None:
+        f_out = torch.empty((n, 3), dtype=torch.float64, device=x.device)
+    _vec3(f_out, n, "f_out")
+    p = params if params is not None else globals()["params"]()
+    lb = lub_params if lub_params is not None else lub()
+    check(lib().lubrication_forces(ctypes.byref(p), ctypes.byref(lb), n, _ptr(x), _ptr(v),
+                                   _ptr(f_ext), _ptr(f_out), _stream(stream)))
+    return f_out
+
+
+def sd_run_lub(x, f_ext, v_prev, dt: float, steps: int, *, step0: int = 0,
+               integrator: int = SD_EULER, params: SdParams = None, lub_params: SdLub = None,
+               precision: int = SD_FP32_KAHAN, stream=None):
+    """`steps` steps with the lubrication correction, in place on x and v_prev."""
+    n = x.shape[0]
+    for t, nm in ((x, "x"), (f_ext, "f_ext"), (v_prev, "v_prev")):
+        _vec3(t, n, nm)
+    p = params if params is not None else globals()["params"]()
+    lb = lub_params if lub_params is not None else lub()
+    check(lib().sd_run_lub(ctypes.byref(p), ctypes.byref(lb), n, _ptr(x), _ptr(f_ext),
+                           _ptr(v_prev), float(dt), int(steps), int(step0), int(integrator),
+                           int(precision), _stream(stream)))
+    return x
 
 
 class Batch:

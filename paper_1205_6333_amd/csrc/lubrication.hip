@@ -1,0 +1,348 @@
+// lubrication.hip -- the lubrication correction of Eq. (8) folded into the
+// forces with the previous step's velocities (Sec. 3.1, step 2):
+//   F_i = F_ext,i - sum'_j zeta(r_i - r_j) (v_i - v_j),
+//   mu0 zeta(r) = [1/(4s) - 9/40 log s] rhat rhat - 1/6 log s (I - rhat rhat),
+//   s = r/a - 2 < s_cut (Sec. 2.3: s_cut = 1), clamped to s >= s_min.
+// The primed sum runs over close pairs only, found with a cell list rebuilt on
+// the device every step (cells of side >= (2 + s_cut) a; the grid is derived
+// from the bounding box on the device, so a step needs no host round trip).
+// Cells are filled with integer atomics and then sorted by particle index, so
+// the summation order, and hence the result, is deterministic.  All of it is
+// O(N x neighbours) FP64 work next to the O(N^2) mobility product.
+#include "sd.h"
+#include "sd_host.h"
+#include "sd_internal.h"
+
+#include <cmath>
+
+namespace sd {
+
+constexpr int LUB_MAX_CELLS = 1 << 21;   // cap of the cell grid (cells grow beyond the cutoff if needed)
+constexpr int SCAN_T = 1024;
+
+struct CellGrid {
+    double lo[3];
+    double h;        // cell side
+    int dims[3];
+    int ncell;
+};
+
+struct LubConst {
+    double a, mu0, s_cut, s_min, rcut2;
+};
+
+// bounding box -> cell grid (one work-group; fixed-order reduction)
+__global__ void __launch_bounds__(256) k_lub_grid(const double* __restrict__ x, int n, double hmin,
+                                                  CellGrid* __restrict__ g)
+{
+    __shared__ double lo[3][256], hi[3][256];
+    const int t = threadIdx.x;
+    double l[3] = { 1e300, 1e300, 1e300 }, u[3] = { -1e300, -1e300, -1e300 };
+    for (int i = t; i < n; i += 256)
+        for (int k = 0; k < 3; ++k) {
+            const double v = x[3 * (size_t)i + k];
+            l[k] = fmin(l[k], v);
+            u[k] = fmax(u[k], v);
+        }
+    for (int k = 0; k < 3; ++k) {
+        lo[k][t] = l[k];
+        hi[k][t] = u[k];
+    }
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (t < w)
+            for (int k = 0; k < 3; ++k) {
+                lo[k][t] = fmin(lo[k][t], lo[k][t + w]);
+                hi[k][t] = fmax(hi[k][t], hi[k][t + w]);
+            }
+        __syncthreads();
+    }
+    if (t == 0) {
+        double ext[3], h = hmin;
+        for (int k = 0; k < 3; ++k) {
+            ext[k] = hi[k][0] - lo[k][0];
+            // non-finite coordinates (NaN / Inf inputs) collapse that axis to one cell
+            if (!(ext[k] >= 0.0) || !(ext[k] < 1e300)) ext[k] = 0.0;
+            if (!(lo[k][0] > -1e300)) lo[k][0] = 0.0;
+        }
+        // grow the cell until the grid fits the cap (bounded: 1.25^400 covers any
+        // finite extent)
+        for (int it = 0; it < 400; ++it) {
+            double cells = 1.0;
+            for (int k = 0; k < 3; ++k) cells *= floor(ext[k] / h) + 1.0;
+            if (cells <= (double)LUB_MAX_CELLS) break;
+            h *= 1.25;
+        }
+        int nc = 1;
+        for (int k = 0; k < 3; ++k) {
+            g->lo[k] = lo[k][0];
+            g->dims[k] = (int)floor(ext[k] / h) + 1;
+            nc *= g->dims[k];
+        }
+        g->h = h;
+        g->ncell = nc;
+    }
+}
+
+__device__ __forceinline__ int cell_coord(double v, double lo, double h, int dim)
+{
+    int c = (int)floor((v - lo) / h);
+    return c < 0 ? 0 : (c >= dim ? dim - 1 : c);
+}
+
+__global__ void __launch_bounds__(256) k_lub_count(const double* __restrict__ x, int n,
+                                                   const CellGrid* __restrict__ g,
+                                                   int* __restrict__ cid, int* __restrict__ count)
+{
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    const double h = g->h;
+    const int cx = cell_coord(x[3 * (size_t)i], g->lo[0], h, g->dims[0]);
+    const int cy = cell_coord(x[3 * (size_t)i + 1], g->lo[1], h, g->dims[1]);
+    const int cz = cell_coord(x[3 * (size_t)i + 2], g->lo[2], h, g->dims[2]);
+    const int c = (cz * g->dims[1] + cy) * g->dims[0] + cx;
+    cid[i] = c;
+    atomicAdd(&count[c], 1);
+}
+
+// exclusive scan of the cell counts (one work-group), start[ncell] = n;
+// the counts are reset to zero for use as scatter cursors
+__global__ void __launch_bounds__(SCAN_T) k_lub_scan(int* __restrict__ count,
+                                                     int* __restrict__ start,
+                                                     const CellGrid* __restrict__ g, int n)
+{
+    __shared__ int part[SCAN_T];
+    const int t = threadIdx.x;
+    const int nc = g->ncell;
+    const int chunk = (nc + SCAN_T - 1) / SCAN_T;
+    const int b = t * chunk, e = min(nc, b + chunk);
+    int sum = 0;
+    for (int c = b; c < e; ++c) sum += count[c];
+    part[t] = sum;
+    __syncthreads();
+    // Hillis-Steele inclusive scan of the per-thread sums
+    for (int w = 1; w < SCAN_T; w <<= 1) {
+        const int v = t >= w ? part[t - w] : 0;
+        __syncthreads();
+        part[t] += v;
+        __syncthreads();
+    }
+    int run = part[t] - sum;
+    for (int c = b; c < e; ++c) {
+        const int k = count[c];
+        start[c] = run;
+        run += k;
+        count[c] = 0;
+    }
+    if (t == 0) start[nc] = n;
+}
+
+__global__ void __launch_bounds__(256) k_lub_scatter(const int* __restrict__ cid, int n,
+                                                     const int* __restrict__ start,
+                                                     int* __restrict__ cursor,
+                                                     int* __restrict__ order)
+{
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    const int c = cid[i];
+    order[start[c] + atomicAdd(&cursor[c], 1)] = i;
+}
+
+// each cell's members in ascending particle index (cells hold a handful)
+__global__ void __launch_bounds__(256) k_lub_sort(const int* __restrict__ start,
+                                                  int* __restrict__ order,
+                                                  const CellGrid* __restrict__ g)
+{
+    const int c = blockIdx.x * 256 + threadIdx.x;
+    if (c >= g->ncell) return;
+    const int b = start[c], e = start[c + 1];
+    for (int k = b + 1; k < e; ++k) {
+        const int v = order[k];
+        int m = k - 1;
+        while (m >= b && order[m] > v) {
+            order[m + 1] = order[m];
+            --m;
+        }
+        order[m + 1] = v;
+    }
+}
+
+__global__ void __launch_bounds__(256)
+k_lub_force(const double* __restrict__ x, const double* __restrict__ v,
+            const double* __restrict__ f_ext, int n, const CellGrid* __restrict__ g,
+            const int* __restrict__ start, const int* __restrict__ order, LubConst lc,
+            double* __restrict__ f_out)
+{
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    const double xi[3] = { x[3 * (size_t)i], x[3 * (size_t)i + 1], x[3 * (size_t)i + 2] };
+    const double vi[3] = { v[3 * (size_t)i], v[3 * (size_t)i + 1], v[3 * (size_t)i + 2] };
+    const double h = g->h;
+    const int dims[3] = { g->dims[0], g->dims[1], g->dims[2] };
+    int cc[3];
+    for (int k = 0; k < 3; ++k) cc[k] = cell_coord(xi[k], g->lo[k], h, dims[k]);
+    double acc[3] = { 0.0, 0.0, 0.0 };
+    for (int dz = -1; dz <= 1; ++dz) {
+        const int z = cc[2] + dz;
+        if (z < 0 || z >= dims[2]) continue;
+        for (int dy = -1; dy <= 1; ++dy) {
+            const int y = cc[1] + dy;
+            if (y < 0 || y >= dims[1]) continue;
+            for (int dx = -1; dx <= 1; ++dx) {
+                const int xx = cc[0] + dx;
+                if (xx < 0 || xx >= dims[0]) continue;
+                const int c = (z * dims[1] + y) * dims[0] + xx;
+                for (int k = start[c]; k < start[c + 1]; ++k) {
+                    const int j = order[k];
+                    if (j == i) continue;
+                    const double d[3] = { xi[0] - x[3 * (size_t)j], xi[1] - x[3 * (size_t)j + 1],
+                                          xi[2] - x[3 * (size_t)j + 2] };
+                    const double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+                    if (!(r2 < lc.rcut2) || r2 == 0.0) continue;
+                    const double r = sqrt(r2);
+                    double s = r / lc.a - 2.0;
+                    if (s >= lc.s_cut) continue;
+                    if (s < lc.s_min) s = lc.s_min;
+                    const double ls = log(s);
+                    const double cP = (1.0 / (4.0 * s) - 9.0 / 40.0 * ls) / lc.mu0;
+                    const double cT = (-1.0 / 6.0 * ls) / lc.mu0;
+                    const double dv[3] = { vi[0] - v[3 * (size_t)j], vi[1] - v[3 * (size_t)j + 1],
+                                           vi[2] - v[3 * (size_t)j + 2] };
+                    const double hd = (d[0] * dv[0] + d[1] * dv[1] + d[2] * dv[2]) / r;  // rhat . dv
+                    for (int k3 = 0; k3 < 3; ++k3) {
+                        const double nrm = hd * d[k3] / r;                             // (rhat rhat dv)_k
+                        acc[k3] -= cP * nrm + cT * (dv[k3] - nrm);
+                    }
+                }
+            }
+        }
+    }
+    for (int k = 0; k < 3; ++k)
+        f_out[3 * (size_t)i + k] = (f_ext ? f_ext[3 * (size_t)i + k] : 0.0) + acc[k];
+}
+
+// Library workspace of the cell list: grid | cid[n] | count[MAX] | start[MAX+1] | order[n]
+static size_t lub_ws_bytes(int64_t n)
+{
+    return 256 + 4 * (size_t)n * 2 + 4 * ((size_t)LUB_MAX_CELLS * 2 + 1) + 256;
+}
+
+sd_status lub_forces_impl(const sd_params* p, const sd_lub* lub, int64_t n, const double* x,
+                          const double* v, const double* f_ext, double* f_out, hipStream_t hs)
+{
+    sd_status st;
+    void* buf = nullptr;
+    if ((st = ws_get(WS_LUB, lub_ws_bytes(n), &buf))) return st;
+    char* q = (char*)buf;
+    CellGrid* g = (CellGrid*)q;
+    q += 256;
+    int* cid = (int*)q;
+    q += 4 * (size_t)n;
+    int* order = (int*)q;
+    q += 4 * (size_t)n;
+    int* count = (int*)q;
+    q += 4 * (size_t)LUB_MAX_CELLS;
+    int* start = (int*)q;
+    const int nn = (int)n;
+    const dim3 gp((unsigned)((n + 255) / 256));
+    hipError_t e = launch_fill_i32(count, 0, LUB_MAX_CELLS, hs);
+    if (e != hipSuccess) return fail(SD_EDEVICE, "fill launch: %s", hipGetErrorString(e));
+    hipLaunchKernelGGL(k_lub_grid, dim3(1), dim3(256), 0, hs, x, nn, (2.0 + lub->s_cut) * p->a, g);
+    hipLaunchKernelGGL(k_lub_count, gp, dim3(256), 0, hs, x, nn, g, cid, count);
+    hipLaunchKernelGGL(k_lub_scan, dim3(1), dim3(SCAN_T), 0, hs, count, start, g, nn);
+    hipLaunchKernelGGL(k_lub_scatter, gp, dim3(256), 0, hs, cid, nn, start, count, order);
+    hipLaunchKernelGGL(k_lub_sort, dim3(LUB_MAX_CELLS / 256), dim3(256), 0, hs, start, order, g);
+    LubConst lc;
+    lc.a = p->a;
+    lc.mu0 = 1.0 / (6.0 * M_PI * p->eta * p->a);
+    lc.s_cut = lub->s_cut;
+    lc.s_min = lub->s_min;
+    const double rc = (2.0 + lub->s_cut) * p->a;
+    lc.rcut2 = rc * rc;
+    hipLaunchKernelGGL(k_lub_force, gp, dim3(256), 0, hs, x, v, f_ext, nn, g, start, order, lc,
+                       f_out);
+    if ((e = hipGetLastError()) != hipSuccess)
+        return fail(SD_EDEVICE, "lubrication launch: %s", hipGetErrorString(e));
+    return SD_OK;
+}
+
+sd_status check_lub(const sd_lub* lub)
+{
+    if (!lub) return fail(SD_EINVAL, "lub is NULL");
+    if (!(lub->s_cut > 0.0) || !std::isfinite(lub->s_cut))
+        return fail(SD_EINVAL, "s_cut must be finite and > 0");
+    if (!(lub->s_min > 0.0) || !(lub->s_min < lub->s_cut))
+        return fail(SD_EINVAL, "s_min must be in (0, s_cut)");
+    return SD_OK;
+}
+
+}  // namespace sd
+
+using namespace sd;
+
+extern "C" {
+
+sd_status lubrication_forces(const sd_params* p, const sd_lub* lub, int64_t n, const double* x,
+                             const double* v, const double* f_ext, double* f_out, void* stream)
+{
+    sd_status st;
+    if ((st = check_params(p)) || (st = check_lub(lub)) || (st = check_n(n))) return st;
+    if ((st = check_ptr(x, 8, "x")) || (st = check_ptr(v, 8, "v")) ||
+        (st = check_ptr(f_out, 8, "f_out")))
+        return st;
+    if (f_ext && (uintptr_t)f_ext % 8) return fail(SD_EALIGN, "f_ext is not 8-byte aligned");
+    return lub_forces_impl(p, lub, n, x, v, f_ext, f_out, (hipStream_t)stream);
+}
+
+sd_status sd_run_lub(const sd_params* p, const sd_lub* lub, int64_t n, double* x,
+                     const double* f_ext, double* v_prev, double dt, int64_t steps, int64_t step0,
+                     int32_t integrator, int32_t precision, void* stream)
+{
+    sd_status st;
+    if ((st = check_params(p)) || (st = check_lub(lub)) || (st = check_n(n)) ||
+        (st = check_precision(precision)))
+        return st;
+    if ((st = check_ptr(x, 8, "x")) || (st = check_ptr(f_ext, 8, "f_ext")) ||
+        (st = check_ptr(v_prev, 8, "v_prev")))
+        return st;
+    if (!(dt > 0.0) || !std::isfinite(dt)) return fail(SD_EINVAL, "dt must be finite and > 0");
+    if (integrator != SD_EULER && integrator != SD_AB2) return fail(SD_EINVAL, "unknown integrator");
+    if (steps < 0 || step0 < 0) return fail(SD_EINVAL, "steps and step0 must be >= 0");
+    if (steps == 0) return SD_OK;
+    hipStream_t hs = (hipStream_t)stream;
+    const bool f64 = precision == SD_FP64;
+    const size_t rec = f64 ? 32 : 16;
+    const PairLaunch L = plan_pair(precision, n);
+    void *partial = nullptr, *stage = nullptr, *fbuf = nullptr;
+    if ((st = ws_get(WS_PARTIAL, partial_bytes(L, n), &partial)) ||
+        (st = ws_get(WS_STAGE, rec * (size_t)n, &stage)) ||
+        (st = ws_get(WS_LUB_F, (rec + 24) * (size_t)n, &fbuf)))
+        return st;
+    double* F = (double*)fbuf;                       // f64[3n] forces of the step
+    void* F4 = (char*)fbuf + 24 * (size_t)n;          // packed records
+    const double mu0 = 1.0 / (6.0 * M_PI * p->eta * p->a);
+    for (int64_t s = 0; s < steps; ++s) {
+        const int64_t k = step0 + s;
+        if ((st = lub_forces_impl(p, lub, n, x, v_prev, f_ext, F, hs))) return st;
+        hipError_t e = f64 ? launch_pack_f64(F, (double4*)F4, (int)n, hs)
+                           : launch_pack_f32(F, (float4*)F4, (int)n, hs);
+        if (e == hipSuccess)
+            e = f64 ? launch_stage_f64(x, (double4*)stage, (int)n, hs)
+                    : launch_stage_f32(x, (float4*)stage, (int)n, hs);
+        if (e != hipSuccess) return fail(SD_EDEVICE, "staging launch: %s", hipGetErrorString(e));
+        if ((st = run_pair(p, n, stage, F4, f64 ? nullptr : x, precision, (double*)partial, L, hs)))
+            return st;
+        // Euler: x += dt v, v_prev = v;  AB2: x += dt (3/2 v - 1/2 v_prev), v_prev = v
+        const int mode = (integrator == SD_EULER) ? 0 : (k == 0 ? 1 : 2);
+        e = f64 ? launch_merge_integrate_f64((double*)partial, L.splits, (int)n, (const double4*)F4,
+                                             mu0, x, mode ? v_prev : nullptr,
+                                             mode ? nullptr : v_prev, dt, mode, nullptr, hs)
+                : launch_merge_integrate_f32((double*)partial, L.splits, (int)n, (const float4*)F4,
+                                             mu0, x, mode ? v_prev : nullptr,
+                                             mode ? nullptr : v_prev, dt, mode, nullptr, hs);
+        if (e != hipSuccess) return fail(SD_EDEVICE, "integrate launch: %s", hipGetErrorString(e));
+    }
+    return SD_OK;
+}
+
+}  // extern "C"

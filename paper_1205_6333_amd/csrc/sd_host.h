@@ -20,10 +20,13 @@ enum {
     WS_ADJ_LAM,       // adjoint state
     WS_ADJ_CKPT,      // checkpoints when the caller passes none
     WS_TUNE,          // autotuner scratch
+    WS_LUB,           // lubrication cell list
+    WS_LUB_F,         // lubrication-corrected forces of a step
     WS_COUNT
 };
 
 sd_status fail(sd_status st, const char* fmt, ...);
+sd_status check_lub(const sd_lub* lub);
 sd_status check_params(const sd_params* p);
 sd_status check_n(int64_t n);
 sd_status check_precision(int32_t prec);
