@@ -26,7 +26,8 @@ EULER, AB2 = 0, 1
 
 class OracleParams(ctypes.Structure):
     _fields_ = [("a", ctypes.c_double), ("eta", ctypes.c_double),
-                ("tensor", ctypes.c_int), ("overlap", ctypes.c_int)]
+                ("tensor", ctypes.c_int), ("overlap", ctypes.c_int),
+                ("box", ctypes.c_double * 3)]
 
 
 class OracleLub(ctypes.Structure):
@@ -84,9 +85,12 @@ def threads() -> int:
 
 
 def params(a: float = 1.0, eta: float = 1.0 / (6.0 * np.pi), tensor: int = RPY,
-           overlap: bool = False) -> OracleParams:
-    """Sphere radius a, viscosity eta; the defaults give mu0 = 1/(6 pi eta a) = 1."""
-    return OracleParams(float(a), float(eta), int(tensor), int(bool(overlap)))
+           overlap: bool = False, box=None) -> OracleParams:
+    """Sphere radius a, viscosity eta; the defaults give mu0 = 1/(6 pi eta a) = 1.
+    box: periodic box sides (nearest image), None / 0 = free space."""
+    b = (0.0, 0.0, 0.0) if box is None else tuple(float(v) for v in np.broadcast_to(box, (3,)))
+    return OracleParams(float(a), float(eta), int(tensor), int(bool(overlap)),
+                        (ctypes.c_double * 3)(*b))
 
 
 def _ptr(arr):

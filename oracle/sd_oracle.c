@@ -44,6 +44,7 @@ typedef struct {
     double eta;    /* shear viscosity */
     int tensor;    /* 0 = Rotne-Prager (Eq. 7b), 1 = Oseen (Eq. 4) */
     int overlap;   /* 0 = far form at every r > 0, 1 = overlap form for r < 2a */
+    double box[3]; /* periodic box sides; 0 = free space along that axis */
 } oracle_params;
 
 enum { OR_RPY = 0, OR_OSEEN = 1 };
@@ -56,6 +57,16 @@ int oracle_threads(void)
 #else
     return 1;
 #endif
+}
+
+/* Nearest image (footnote of Sec. 3.1): in a periodic box only the nearest
+ * image of each particle interacts.  r = r_i - r_j is replaced by the
+ * periodic copy of least length along every periodic axis (ties at exactly
+ * half a box side round to even, a measure-zero reading). */
+static void nearest_image(const oracle_params* p, double r[3])
+{
+    for (int k = 0; k < 3; ++k)
+        if (p->box[k] > 0.0) r[k] -= p->box[k] * nearbyint(r[k] / p->box[k]);
 }
 
 /* Stokes mobility of a single sphere, mu0 = 1/(6 pi eta a): Eq. (7a), Sec. 2.2. */
@@ -117,6 +128,7 @@ static void velocity_of(const oracle_params* p, int64_t n, const double* x, cons
         if (j == i) continue;
         double r[3] = { x[3 * i + 0] - x[3 * j + 0], x[3 * i + 1] - x[3 * j + 1],
                         x[3 * i + 2] - x[3 * j + 2] };
+        nearest_image(p, r);
         double T[9];
         oracle_pair_tensor(p, r, T);
         for (int al = 0; al < 3; ++al)
@@ -157,6 +169,7 @@ void oracle_dense_mobility(const oracle_params* p, int64_t n, const double* x, d
             } else {
                 double r[3] = { x[3 * i] - x[3 * j], x[3 * i + 1] - x[3 * j + 1],
                                 x[3 * i + 2] - x[3 * j + 2] };
+                nearest_image(p, r);
                 oracle_pair_tensor(p, r, T);
             }
             for (int al = 0; al < 3; ++al)
@@ -256,6 +269,7 @@ void oracle_mobility_transpose(const oracle_params* p, int64_t n, const double* 
             if (j == i) continue;
             double r[3] = { x[3 * j] - x[3 * i], x[3 * j + 1] - x[3 * i + 1],
                             x[3 * j + 2] - x[3 * i + 2] };
+            nearest_image(p, r);
             double T[9];
             oracle_pair_tensor(p, r, T);
             for (int be = 0; be < 3; ++be)  /* column be of block mu_ji = row be of its transpose */
@@ -284,7 +298,10 @@ void oracle_mobility_vjp_x(const oracle_params* p, int64_t n, const double* x, c
             if (j == i) continue;
             double rij[3] = { x[3 * i] - x[3 * j], x[3 * i + 1] - x[3 * j + 1],
                               x[3 * i + 2] - x[3 * j + 2] };
-            double rji[3] = { -rij[0], -rij[1], -rij[2] };
+            double rji[3] = { x[3 * j] - x[3 * i], x[3 * j + 1] - x[3 * i + 1],
+                              x[3 * j + 2] - x[3 * i + 2] };
+            nearest_image(p, rij);
+            nearest_image(p, rji);
             double g1[3], g2[3];
             oracle_pair_grad(p, rij, lam + 3 * i, f + 3 * j, g1);
             oracle_pair_grad(p, rji, lam + 3 * j, f + 3 * i, g2);
@@ -378,8 +395,9 @@ void oracle_lubrication_force(const oracle_params* p, const oracle_lub* lub, int
         double acc[3] = { 0.0, 0.0, 0.0 };
         for (int64_t j = 0; j < n; ++j) {
             if (j == i) continue;
-            const double r[3] = { x[3 * i] - x[3 * j], x[3 * i + 1] - x[3 * j + 1],
-                                  x[3 * i + 2] - x[3 * j + 2] };
+            double r[3] = { x[3 * i] - x[3 * j], x[3 * i + 1] - x[3 * j + 1],
+                            x[3 * i + 2] - x[3 * j + 2] };
+            nearest_image(p, r);
             double Z[9];
             oracle_lub_tensor(p, lub, r, Z);
             const double dv[3] = { v[3 * i] - v[3 * j], v[3 * i + 1] - v[3 * j + 1],

@@ -152,6 +152,18 @@ def square_xz(side: float = 5.0, a: float = 1.0):
     return x, gravity_forces(4)
 
 
+def fcc_lattice(m: int, density: float = 0.1, a: float = 1.0):
+    """Sec. 3.3 benchmark start: a perfect fcc lattice of m^3 cubic unit cells
+    (N = 4 m^3 particles) at number density n = N / L^3 (0.1 / a^3 in the
+    paper).  Returns (positions (N, 3) in [0, L)^3, box side L)."""
+    c = (4.0 / density) ** (1.0 / 3.0) * a
+    basis = np.array([[0.0, 0.0, 0.0], [0.0, 0.5, 0.5], [0.5, 0.0, 0.5], [0.5, 0.5, 0.0]])
+    g = np.arange(m, dtype=np.float64)
+    cells = np.stack(np.meshgrid(g, g, g, indexing="ij"), -1).reshape(-1, 3)
+    x = (cells[:, None, :] + basis[None, :, :]).reshape(-1, 3) * c
+    return x, m * c
+
+
 def to_float4(v: np.ndarray, dtype=np.float32) -> np.ndarray:
     """(n, 3) -> (n, 4) with w = 0, in the given dtype (the device layout)."""
     out = np.zeros((v.shape[0], 4), dtype=dtype)
