@@ -24,6 +24,8 @@ Other rows of the hot path are measured with --workload (one JSON line each):
             steps dt = 0.01 in one persistent graph-launched kernel
   adjoint   N = 8192, 200 Euler steps dt = 0.01, loss |x_N - x_target|^2,
             checkpoint every 20 steps: forward and backward times
+  lubrication  N = 65536 suspension, lubrication correction (Eq. 8) with the
+            previous velocities, Euler dt = 0.001 (--loop-steps steps)
   copy      a plain device copy of --copy-mib MiB (calibrates HBM counters)
 """
 from __future__ import annotations
@@ -234,6 +236,37 @@ def run_adjoint(args, sd, W, dev):
     return out
 
 
+def run_lubrication(args, sd, W, dev):
+    import torch
+    n, steps = args.n, args.loop_steps
+    x0 = W.random_suspension(n, phi=0.05, seed=1)
+    f = W.gravity_forces(n) + 0.1 * W.gaussian_forces(n, seed=2)
+    fd = torch.tensor(f, device=dev)
+    f4 = _to4(f, torch.float32, dev)
+    x = torch.tensor(x0, device=dev)
+    vp = torch.zeros_like(x)
+    sd.sd_run_lub(x, fd, vp, 0.001, 3)  # warm-up
+    n_close = int(sd.lubrication_forces(torch.tensor(x0, device=dev), torch.ones_like(x)).ne(0)
+                  .any(1).sum())
+    x = torch.tensor(x0, device=dev)
+    vp.zero_()
+    t_lub = _sync_time(lambda: sd.sd_run_lub(x, fd, vp, 0.001, steps))
+    x2 = torch.tensor(x0, device=dev)
+    t_plain = _sync_time(lambda: sd.sd_run(x2, f4, 0.001, steps))
+    fo = torch.empty_like(x)
+    t_forces = _sync_time(lambda: [sd.lubrication_forces(x, vp, fd, fo) for _ in range(steps)])
+    return {"metric": "Euler steps/s with lubrication at N=%d (FP32-comp pair kernel)" % n,
+            "value": steps / t_lub, "unit": "steps/s", "n_gpus": 1, "higher_is_better": True,
+            "dtype": "f32", "data": "synthetic", "steps": steps,
+            "ms_per_step": t_lub * 1e3 / steps, "ms_per_step_without_lubrication": t_plain * 1e3 / steps,
+            "lubrication_forces_ms": t_forces * 1e3 / steps,
+            "g_pairs_per_s": float(n) * n * steps / t_lub / 1e9,
+            "particles_with_close_pairs_at_start": n_close,
+            "config": {"workload": "N=%d random suspension phi=0.05 (RSA 2.2a), F=(0,0,-1) + 0.1 N(0,1), "
+                                   "lubrication s<1 (s_min 1e-3) with the previous velocities, Euler "
+                                   "dt=0.001, %d steps" % (n, steps)}}
+
+
 def run_copy(args, dev):
     import torch
     m = int(args.copy_mib * 2 ** 20 // 4)
@@ -258,7 +291,7 @@ def main():
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 GPU path")
     ap.add_argument("--tune", action="store_true", help="autotune the kernel shape first (untimed)")
     ap.add_argument("--workload", default="product",
-                    choices=["product", "timeloop", "batched", "adjoint", "copy"])
+                    choices=["product", "timeloop", "batched", "adjoint", "lubrication", "copy"])
     ap.add_argument("--loop-steps", type=int, default=1000, help="steps of --workload timeloop")
     ap.add_argument("--copy-mib", type=float, default=256.0)
     args = ap.parse_args()
@@ -277,6 +310,7 @@ def main():
         fn = {"timeloop": lambda: run_timeloop(args, sd, W, dev),
               "batched": lambda: run_batched(args, sd, W, dev),
               "adjoint": lambda: run_adjoint(args, sd, W, dev),
+              "lubrication": lambda: run_lubrication(args, sd, W, dev),
               "copy": lambda: run_copy(args, dev)}[args.workload]
         print(json.dumps(fn()))
         return 0
