@@ -85,6 +85,21 @@ typedef struct sd_params {
     double eta;           /* shear viscosity, > 0 */
     int32_t tensor;       /* sd_tensor */
     int32_t overlap;      /* sd_overlap */
+    double box[3];        /* periodic box: {0, 0, 0} = free space, or a cubic box
+                             {L, L, L} with L > 2a, in which each pair
+                             interacts through its nearest image only
+                             (footnote of Sec. 3.1: no sum over images).
+                             Positions may lie outside [0, L); the time loop
+                             keeps them unwrapped.  A pair exactly half a box
+                             apart along an axis has two nearest images; which
+                             one a path takes follows from its rounding (the
+                             FP32 paths stage positions as 32-bit fixed-point
+                             fractions of L and take -L/2 at an exact tie).
+                             Other boxes: SD_EUNSUPPORTED (SD_EINVAL for
+                             negative or non-finite sides, or L <= 2a).
+                             Supported by the product, the time loop and the
+                             lubrication correction; the adjoint and batched
+                             entry points return SD_EUNSUPPORTED for a box. */
 } sd_params;
 
 /* ------------------------------------------------------------------ product */

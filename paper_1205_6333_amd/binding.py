@@ -27,7 +27,8 @@ SD_BATCH_MAX_CLUSTER = 1024
 
 class SdParams(ctypes.Structure):
     _fields_ = [("a", ctypes.c_double), ("eta", ctypes.c_double),
-                ("tensor", ctypes.c_int32), ("overlap", ctypes.c_int32)]
+                ("tensor", ctypes.c_int32), ("overlap", ctypes.c_int32),
+                ("box", ctypes.c_double * 3)]
 
 
 class SdLub(ctypes.Structure):
@@ -115,9 +116,18 @@ def check(status: int) -> None:
 
 
 def params(a: float = 1.0, eta: float = 1.0 / (6.0 * math.pi), tensor: int = SD_RPY,
-           overlap: bool = False) -> SdParams:
-    """Sphere radius, viscosity, pair tensor and overlap mode (defaults: mu0 = 1)."""
-    return SdParams(float(a), float(eta), int(tensor), int(bool(overlap)))
+           overlap: bool = False, box=None) -> SdParams:
+    """Sphere radius, viscosity, pair tensor and overlap mode (defaults: mu0 = 1).
+    ``box``: side of a periodic cubic box (a number or three equal sides;
+    nearest-image interactions), None for free space."""
+    if box is None:
+        sides = (0.0, 0.0, 0.0)
+    elif isinstance(box, (int, float)):
+        sides = (float(box),) * 3
+    else:
+        sides = tuple(float(b) for b in box)
+    return SdParams(float(a), float(eta), int(tensor), int(bool(overlap)),
+                    (ctypes.c_double * 3)(*sides))
 
 
 def _stream(stream) -> ctypes.c_void_p:

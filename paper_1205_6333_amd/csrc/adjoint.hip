@@ -526,7 +526,9 @@ sd_status mobility_adjoint(const sd_params* p, int64_t n, const void* pos, const
                            int32_t precision, void* stream)
 {
     sd_status st;
-    if ((st = check_params(p)) || (st = check_n(n)) || (st = check_precision(precision))) return st;
+    if ((st = check_params(p)) || (st = check_free_space(p, "the adjoint")) || (st = check_n(n)) ||
+        (st = check_precision(precision)))
+        return st;
     const size_t al = vec4_align(precision);
     if ((st = check_ptr(pos, al, "pos")) || (st = check_ptr(force, al, "force")) ||
         (st = check_ptr(lam, al, "lam")) || (st = check_ptr(grad_pos, 8, "grad_pos")))
@@ -543,7 +545,9 @@ sd_status sd_run_adjoint(const sd_params* p, int64_t n, const double* x0, const 
                          double* grad_force, void* stream)
 {
     sd_status st;
-    if ((st = check_params(p)) || (st = check_n(n)) || (st = check_precision(precision))) return st;
+    if ((st = check_params(p)) || (st = check_free_space(p, "the adjoint")) || (st = check_n(n)) ||
+        (st = check_precision(precision)))
+        return st;
     if ((st = check_ptr(x0, 8, "x0")) || (st = check_ptr(force, vec4_align(precision), "force")) ||
         (st = check_ptr(grad_xN, 8, "grad_xN")) || (st = check_ptr(grad_x0, 8, "grad_x0")) ||
         (st = check_ptr(grad_force, 8, "grad_force")))

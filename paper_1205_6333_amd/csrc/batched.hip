@@ -525,7 +525,7 @@ sd_status sd_batch_create(const sd_params* p, int64_t n_clusters, const int64_t*
                           sd_batch** out)
 {
     sd_status st;
-    if ((st = check_params(p))) return st;
+    if ((st = check_params(p)) || (st = check_free_space(p, "the batched path"))) return st;
     if (!out) return fail(SD_EINVAL, "out is NULL");
     *out = nullptr;
     if (n_clusters < 1 || n_clusters > (int64_t(1) << 30))

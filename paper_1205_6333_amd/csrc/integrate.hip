@@ -5,30 +5,43 @@
 
 namespace sd {
 
-__global__ void __launch_bounds__(256) k_stage_f32(const double* __restrict__ x,
-                                                   float4* __restrict__ pos, int n)
+// Fixed-point coordinate of a periodic box (q = x 2^32 / Lb mod 2^32, see
+// PairConst), returned as the bits of a float record.  qs = 2^32 / Lb.
+__device__ __forceinline__ float fixed_coord(double x, double qs)
 {
-    const int i = blockIdx.x * 256 + threadIdx.x;
-    if (i >= n) return;
-    pos[i] = make_float4((float)x[3 * (size_t)i], (float)x[3 * (size_t)i + 1],
-                         (float)x[3 * (size_t)i + 2], 0.0f);
+    const long long t = (long long)rint(x * qs);
+    return __uint_as_float((unsigned int)(unsigned long long)t);
 }
 
-__global__ void __launch_bounds__(256) k_stage_f64(const double* __restrict__ x,
-                                                   double4* __restrict__ pos, int n)
+// FP32 record of a position: plain FP32 (qs = 0) or fixed point (qs > 0).
+__device__ __forceinline__ void put_pos(float4* p, int i, double a, double b, double c, double qs)
 {
-    const int i = blockIdx.x * 256 + threadIdx.x;
-    if (i >= n) return;
-    pos[i] = make_double4(x[3 * (size_t)i], x[3 * (size_t)i + 1], x[3 * (size_t)i + 2], 0.0);
+    if (qs > 0.0)
+        p[i] = make_float4(fixed_coord(a, qs), fixed_coord(b, qs), fixed_coord(c, qs), 0.0f);
+    else
+        p[i] = make_float4((float)a, (float)b, (float)c, 0.0f);
 }
-
-__device__ __forceinline__ void put_pos(float4* p, int i, double a, double b, double c)
-{
-    p[i] = make_float4((float)a, (float)b, (float)c, 0.0f);
-}
-__device__ __forceinline__ void put_pos(double4* p, int i, double a, double b, double c)
+__device__ __forceinline__ void put_pos(double4* p, int i, double a, double b, double c, double)
 {
     p[i] = make_double4(a, b, c, 0.0);
+}
+
+template <typename P4>
+__global__ void __launch_bounds__(256) k_stage(const double* __restrict__ x, P4* __restrict__ pos,
+                                               int n, double qs)
+{
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    put_pos(pos, i, x[3 * (size_t)i], x[3 * (size_t)i + 1], x[3 * (size_t)i + 2], qs);
+}
+
+__global__ void __launch_bounds__(256) k_stage_q_from_f32(const float4* __restrict__ pos,
+                                                          float4* __restrict__ q, int n, double qs)
+{
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    const float4 p = pos[i];
+    put_pos(q, i, (double)p.x, (double)p.y, (double)p.z, qs);
 }
 
 // v_k = mu0 F + sum_s partial_s (the same order as k_merge), then
@@ -40,7 +53,8 @@ template <typename F4, typename P4>
 __global__ void __launch_bounds__(256)
 k_merge_integrate(const double* __restrict__ partial, int S, int n, const F4* __restrict__ frc,
                   double mu0, double* __restrict__ x, double* __restrict__ v_prev,
-                  double* __restrict__ v_out, double dt, int mode, P4* __restrict__ pos_next)
+                  double* __restrict__ v_out, double dt, int mode, P4* __restrict__ pos_next,
+                  double qs)
 {
     const int i = blockIdx.x * 256 + threadIdx.x;
     if (i >= n) return;
@@ -62,7 +76,7 @@ k_merge_integrate(const double* __restrict__ partial, int S, int n, const F4* __
         if (mode != 0) v_prev[e] = v[k];
         if (v_out) v_out[e] = v[k];
     }
-    if (pos_next) put_pos(pos_next, i, xn[0], xn[1], xn[2]);
+    if (pos_next) put_pos(pos_next, i, xn[0], xn[1], xn[2], qs);
 }
 
 __global__ void __launch_bounds__(256) k_sum_partials(const double* __restrict__ partial, int S,
@@ -91,7 +105,7 @@ __global__ void __launch_bounds__(256) k_pack(const double* __restrict__ v, P4* 
 {
     const int i = blockIdx.x * 256 + threadIdx.x;
     if (i >= n) return;
-    put_pos(out, i, v[3 * (size_t)i], v[3 * (size_t)i + 1], v[3 * (size_t)i + 2]);
+    put_pos(out, i, v[3 * (size_t)i], v[3 * (size_t)i + 1], v[3 * (size_t)i + 2], 0.0);
 }
 
 __global__ void __launch_bounds__(256) k_axpy(double s, const double* __restrict__ x,
@@ -143,24 +157,37 @@ hipError_t launch_mean_vector(const double* v, int64_t n, double* out, hipStream
 
 static inline dim3 grid_for(int64_t n) { return dim3((unsigned)((n + 255) / 256)); }
 
-hipError_t launch_stage_f32(const double* x, float4* pos, int n, hipStream_t st)
+// 2^32 / Lb, the fixed-point scale of a periodic box (0 in free space)
+static inline double q_scale(double box) { return box > 0.0 ? 4294967296.0 / box : 0.0; }
+
+hipError_t launch_stage_f32(const double* x, float4* pos, int n, double box, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_stage_f32, grid_for(n), dim3(256), 0, st, x, pos, n);
+    hipLaunchKernelGGL((k_stage<float4>), grid_for(n), dim3(256), 0, st, x, pos, n,
+                       q_scale(box));
     return hipGetLastError();
 }
 
 hipError_t launch_stage_f64(const double* x, double4* pos, int n, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_stage_f64, grid_for(n), dim3(256), 0, st, x, pos, n);
+    hipLaunchKernelGGL((k_stage<double4>), grid_for(n), dim3(256), 0, st, x, pos, n, 0.0);
+    return hipGetLastError();
+}
+
+hipError_t launch_stage_q_from_f32(const float4* pos, float4* q, int n, double box,
+                                   hipStream_t st)
+{
+    hipLaunchKernelGGL(k_stage_q_from_f32, grid_for(n), dim3(256), 0, st, pos, q, n,
+                       q_scale(box));
     return hipGetLastError();
 }
 
 hipError_t launch_merge_integrate_f32(const double* partial, int splits, int n, const float4* frc,
                                       double mu0, double* x, double* v_prev, double* v_out,
-                                      double dt, int mode, float4* pos_next, hipStream_t st)
+                                      double dt, int mode, float4* pos_next, double box,
+                                      hipStream_t st)
 {
     hipLaunchKernelGGL((k_merge_integrate<float4, float4>), grid_for(n), dim3(256), 0, st, partial,
-                       splits, n, frc, mu0, x, v_prev, v_out, dt, mode, pos_next);
+                       splits, n, frc, mu0, x, v_prev, v_out, dt, mode, pos_next, q_scale(box));
     return hipGetLastError();
 }
 
@@ -169,7 +196,7 @@ hipError_t launch_merge_integrate_f64(const double* partial, int splits, int n, 
                                       double dt, int mode, double4* pos_next, hipStream_t st)
 {
     hipLaunchKernelGGL((k_merge_integrate<double4, double4>), grid_for(n), dim3(256), 0, st,
-                       partial, splits, n, frc, mu0, x, v_prev, v_out, dt, mode, pos_next);
+                       partial, splits, n, frc, mu0, x, v_prev, v_out, dt, mode, pos_next, 0.0);
     return hipGetLastError();
 }
 

@@ -7,7 +7,9 @@
 // the device every step (cells of side >= (2 + s_cut) a; the grid is derived
 // from the bounding box on the device, so a step needs no host round trip).
 // Cells are filled with integer atomics and then sorted by particle index, so
-// the summation order, and hence the result, is deterministic.  All of it is
+// the summation order, and hence the result, is deterministic.  In a periodic
+// cubic box the grid tiles the box, cell neighbours wrap around, and each pair
+// interacts through its nearest image only.  All of it is
 // O(N x neighbours) FP64 work next to the O(N^2) mobility product.
 #include "sd.h"
 #include "sd_host.h"
@@ -23,18 +25,34 @@ constexpr int SCAN_T = 1024;
 struct CellGrid {
     double lo[3];
     double h;        // cell side
+    double box;      // periodic cubic box side, 0 = free space
     int dims[3];
     int ncell;
 };
 
 struct LubConst {
     double a, mu0, s_cut, s_min, rcut2;
+    PairConst pc;    // box for the nearest image
 };
 
 // bounding box -> cell grid (one work-group; fixed-order reduction)
 __global__ void __launch_bounds__(256) k_lub_grid(const double* __restrict__ x, int n, double hmin,
-                                                  CellGrid* __restrict__ g)
+                                                  double box, CellGrid* __restrict__ g)
 {
+    if (box > 0.0) {  // periodic: the grid tiles the box, cells no smaller than hmin
+        if (threadIdx.x == 0) {
+            int d = (int)floor(box / hmin);
+            d = d < 1 ? 1 : (d > 128 ? 128 : d);  // 128^3 <= LUB_MAX_CELLS
+            for (int k = 0; k < 3; ++k) {
+                g->lo[k] = 0.0;
+                g->dims[k] = d;
+            }
+            g->h = box / d;
+            g->box = box;
+            g->ncell = d * d * d;
+        }
+        return;
+    }
     __shared__ double lo[3][256], hi[3][256];
     const int t = threadIdx.x;
     double l[3] = { 1e300, 1e300, 1e300 }, u[3] = { -1e300, -1e300, -1e300 };
@@ -80,14 +98,37 @@ __global__ void __launch_bounds__(256) k_lub_grid(const double* __restrict__ x, 
             nc *= g->dims[k];
         }
         g->h = h;
+        g->box = 0.0;
         g->ncell = nc;
     }
 }
 
-__device__ __forceinline__ int cell_coord(double v, double lo, double h, int dim)
+__device__ __forceinline__ int cell_coord(double v, double lo, double h, int dim, double box)
 {
+    if (box > 0.0) v -= box * floor(v / box);  // wrap into [0, box)
     int c = (int)floor((v - lo) / h);
     return c < 0 ? 0 : (c >= dim ? dim - 1 : c);
+}
+
+// Distinct neighbour cells of cell c along one axis: c-1, c, c+1, clipped to
+// the grid in free space, wrapped (and de-duplicated on grids narrower than
+// three cells) in a periodic box.  Returns the count.
+__device__ __forceinline__ int axis_neighbours(int c, int dim, bool periodic, int (&out)[3])
+{
+    int m = 0;
+    if (periodic) {
+        if (dim < 3) {
+            for (int k = 0; k < dim; ++k) out[m++] = k;
+        } else {
+            out[m++] = c == 0 ? dim - 1 : c - 1;
+            out[m++] = c;
+            out[m++] = c == dim - 1 ? 0 : c + 1;
+        }
+    } else {
+        for (int k = c - 1; k <= c + 1; ++k)
+            if (k >= 0 && k < dim) out[m++] = k;
+    }
+    return m;
 }
 
 __global__ void __launch_bounds__(256) k_lub_count(const double* __restrict__ x, int n,
@@ -97,9 +138,9 @@ __global__ void __launch_bounds__(256) k_lub_count(const double* __restrict__ x,
     const int i = blockIdx.x * 256 + threadIdx.x;
     if (i >= n) return;
     const double h = g->h;
-    const int cx = cell_coord(x[3 * (size_t)i], g->lo[0], h, g->dims[0]);
-    const int cy = cell_coord(x[3 * (size_t)i + 1], g->lo[1], h, g->dims[1]);
-    const int cz = cell_coord(x[3 * (size_t)i + 2], g->lo[2], h, g->dims[2]);
+    const int cx = cell_coord(x[3 * (size_t)i], g->lo[0], h, g->dims[0], g->box);
+    const int cy = cell_coord(x[3 * (size_t)i + 1], g->lo[1], h, g->dims[1], g->box);
+    const int cz = cell_coord(x[3 * (size_t)i + 2], g->lo[2], h, g->dims[2], g->box);
     const int c = (cz * g->dims[1] + cy) * g->dims[0] + cx;
     cid[i] = c;
     atomicAdd(&count[c], 1);
@@ -179,24 +220,25 @@ k_lub_force(const double* __restrict__ x, const double* __restrict__ v,
     const double vi[3] = { v[3 * (size_t)i], v[3 * (size_t)i + 1], v[3 * (size_t)i + 2] };
     const double h = g->h;
     const int dims[3] = { g->dims[0], g->dims[1], g->dims[2] };
-    int cc[3];
-    for (int k = 0; k < 3; ++k) cc[k] = cell_coord(xi[k], g->lo[k], h, dims[k]);
+    const bool per = g->box > 0.0;
+    int nb[3][3], nn[3];
+    for (int k = 0; k < 3; ++k)
+        nn[k] = axis_neighbours(cell_coord(xi[k], g->lo[k], h, dims[k], g->box), dims[k], per,
+                                nb[k]);
     double acc[3] = { 0.0, 0.0, 0.0 };
-    for (int dz = -1; dz <= 1; ++dz) {
-        const int z = cc[2] + dz;
-        if (z < 0 || z >= dims[2]) continue;
-        for (int dy = -1; dy <= 1; ++dy) {
-            const int y = cc[1] + dy;
-            if (y < 0 || y >= dims[1]) continue;
-            for (int dx = -1; dx <= 1; ++dx) {
-                const int xx = cc[0] + dx;
-                if (xx < 0 || xx >= dims[0]) continue;
+    for (int iz = 0; iz < nn[2]; ++iz) {
+        const int z = nb[2][iz];
+        for (int iy = 0; iy < nn[1]; ++iy) {
+            const int y = nb[1][iy];
+            for (int ix = 0; ix < nn[0]; ++ix) {
+                const int xx = nb[0][ix];
                 const int c = (z * dims[1] + y) * dims[0] + xx;
                 for (int k = start[c]; k < start[c + 1]; ++k) {
                     const int j = order[k];
                     if (j == i) continue;
-                    const double d[3] = { xi[0] - x[3 * (size_t)j], xi[1] - x[3 * (size_t)j + 1],
-                                          xi[2] - x[3 * (size_t)j + 2] };
+                    double d[3] = { xi[0] - x[3 * (size_t)j], xi[1] - x[3 * (size_t)j + 1],
+                                    xi[2] - x[3 * (size_t)j + 2] };
+                    nearest_image_d(lc.pc, d[0], d[1], d[2]);
                     const double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
                     if (!(r2 < lc.rcut2) || r2 == 0.0) continue;
                     const double r = sqrt(r2);
@@ -247,7 +289,8 @@ sd_status lub_forces_impl(const sd_params* p, const sd_lub* lub, int64_t n, cons
     const dim3 gp((unsigned)((n + 255) / 256));
     hipError_t e = launch_fill_i32(count, 0, LUB_MAX_CELLS, hs);
     if (e != hipSuccess) return fail(SD_EDEVICE, "fill launch: %s", hipGetErrorString(e));
-    hipLaunchKernelGGL(k_lub_grid, dim3(1), dim3(256), 0, hs, x, nn, (2.0 + lub->s_cut) * p->a, g);
+    hipLaunchKernelGGL(k_lub_grid, dim3(1), dim3(256), 0, hs, x, nn, (2.0 + lub->s_cut) * p->a,
+                       box_side(p), g);
     hipLaunchKernelGGL(k_lub_count, gp, dim3(256), 0, hs, x, nn, g, cid, count);
     hipLaunchKernelGGL(k_lub_scan, dim3(1), dim3(SCAN_T), 0, hs, count, start, g, nn);
     hipLaunchKernelGGL(k_lub_scatter, gp, dim3(256), 0, hs, cid, nn, start, count, order);
@@ -259,6 +302,7 @@ sd_status lub_forces_impl(const sd_params* p, const sd_lub* lub, int64_t n, cons
     lc.s_min = lub->s_min;
     const double rc = (2.0 + lub->s_cut) * p->a;
     lc.rcut2 = rc * rc;
+    lc.pc = pair_const(p);
     hipLaunchKernelGGL(k_lub_force, gp, dim3(256), 0, hs, x, v, f_ext, nn, g, start, order, lc,
                        f_out);
     if ((e = hipGetLastError()) != hipSuccess)
@@ -328,7 +372,7 @@ sd_status sd_run_lub(const sd_params* p, const sd_lub* lub, int64_t n, double* x
                            : launch_pack_f32(F, (float4*)F4, (int)n, hs);
         if (e == hipSuccess)
             e = f64 ? launch_stage_f64(x, (double4*)stage, (int)n, hs)
-                    : launch_stage_f32(x, (float4*)stage, (int)n, hs);
+                    : launch_stage_f32(x, (float4*)stage, (int)n, box_side(p), hs);
         if (e != hipSuccess) return fail(SD_EDEVICE, "staging launch: %s", hipGetErrorString(e));
         if ((st = run_pair(p, n, stage, F4, f64 ? nullptr : x, precision, (double*)partial, L, hs)))
             return st;
@@ -339,7 +383,8 @@ sd_status sd_run_lub(const sd_params* p, const sd_lub* lub, int64_t n, double* x
                                              mode ? nullptr : v_prev, dt, mode, nullptr, hs)
                 : launch_merge_integrate_f32((double*)partial, L.splits, (int)n, (const float4*)F4,
                                              mu0, x, mode ? v_prev : nullptr,
-                                             mode ? nullptr : v_prev, dt, mode, nullptr, hs);
+                                             mode ? nullptr : v_prev, dt, mode, nullptr,
+                                             box_side(p), hs);
         if (e != hipSuccess) return fail(SD_EDEVICE, "integrate launch: %s", hipGetErrorString(e));
     }
     return SD_OK;

@@ -19,20 +19,26 @@
 
 namespace sd {
 
-PairConst make_pair_const(double a, double eta, int tensor, int overlap)
+PairConst make_pair_const(double a, double eta, int tensor, int overlap, double box)
 {
     PairConst c;
     const double gamma = (tensor == T_RPY) ? 2.0 * a * a / 3.0 : 0.0;
     const double thr2 = 4.0 * a * a * (1.0 + NEAR_EPS);
-    c.gamma_f = (float)gamma;
-    c.m3gamma_f = (float)(-3.0 * gamma);
-    c.thr2_f = (float)thr2;
+    // FP32 length unit: 1 in free space, the fixed-point unit s in a box
+    const double s = box > 0.0 ? box / 4294967296.0 : 1.0;
+    c.gamma_f = (float)(gamma / (s * s));
+    c.m3gamma_f = (float)(-3.0 * gamma / (s * s));
+    c.thr2_f = (float)(thr2 / (s * s));
     c.overlap = (tensor == T_RPY && overlap) ? 1 : 0;
     c.thr2_d = thr2;
     c.alpha = 1.0 / (8.0 * M_PI * eta);
+    c.alpha_sum = c.alpha / s;
     c.gamma = gamma;
     c.mu0 = 1.0 / (6.0 * M_PI * eta * a);
     c.a = a;
+    c.box = box > 0.0 ? box : 0.0;
+    c.ibox = box > 0.0 ? 1.0 / box : 0.0;
+    c.s_q = box > 0.0 ? s : 0.0;
     return c;
 }
 
@@ -72,8 +78,25 @@ __device__ __forceinline__ void map_block(int S, int& ib, int& s)
 
 // Placeholders for padded lanes / padded tile slots.  Far apart, zero force:
 // every term they produce is exactly zero or never stored, and never NaN.
+// In a periodic box no point is far from another; there the placeholders are
+// the origin, and a placeholder that lands below the near threshold takes the
+// near branch, which skips padded indices and masks the pair to +inf.
 #define SD_FAR_I (-1.0e15f)
 #define SD_FAR_J (1.0e15f)
+
+template <bool PER>
+__device__ __forceinline__ float far_i() { return PER ? 0.0f : SD_FAR_I; }
+template <bool PER>
+__device__ __forceinline__ float far_j() { return PER ? 0.0f : SD_FAR_J; }
+
+// FP32 coordinate difference a - b.  Periodic: a and b hold fixed-point bits;
+// the 32-bit wrapped difference is the nearest image in units of s.
+template <bool PER>
+__device__ __forceinline__ float pdiff(float a, float b)
+{
+    if (PER) return (float)(int)(__float_as_uint(a) - __float_as_uint(b));
+    return a - b;
+}
 
 // FP64 contribution of one near pair (d = x_i - x_j, r^2 below threshold) to v_i.
 template <int TENSOR>
@@ -118,16 +141,40 @@ struct LaneF32 {
     int i;
 };
 
+// FP64 difference x_i - x_j of a near pair: from the FP64 positions when
+// given (nearest image in a box), else from the FP32 records (exact
+// difference of floats, or the fixed-point difference times s).
+template <bool PER>
+__device__ __forceinline__ void near_diff(const LaneF32& L, const float4 pj, int jg,
+                                          const PairConst& pc, const double* __restrict__ x64,
+                                          double& d0, double& d1, double& d2)
+{
+    if (x64) {
+        d0 = x64[3 * (size_t)L.i + 0] - x64[3 * (size_t)jg + 0];
+        d1 = x64[3 * (size_t)L.i + 1] - x64[3 * (size_t)jg + 1];
+        d2 = x64[3 * (size_t)L.i + 2] - x64[3 * (size_t)jg + 2];
+        if (PER) nearest_image_d(pc, d0, d1, d2);
+    } else if (PER) {
+        d0 = (double)(int)(__float_as_uint(L.x) - __float_as_uint(pj.x)) * pc.s_q;
+        d1 = (double)(int)(__float_as_uint(L.y) - __float_as_uint(pj.y)) * pc.s_q;
+        d2 = (double)(int)(__float_as_uint(L.z) - __float_as_uint(pj.z)) * pc.s_q;
+    } else {
+        d0 = (double)L.x - (double)pj.x;
+        d1 = (double)L.y - (double)pj.y;
+        d2 = (double)L.z - (double)pj.z;
+    }
+}
+
 // One pair (i, j) on the FP32 fast path.  pj/fj: position and force of j
 // (wave-uniform).  jg: global index of j, used only on the near branch.
-template <int TENSOR, bool KAHAN>
+template <int TENSOR, bool KAHAN, bool PER>
 __device__ __forceinline__ void pair_f32(LaneF32& L, const float4 pj, const float4 fj, int jg,
                                          int n, const PairConst& pc, float gamma, float m3g,
                                          float thr2, const double* __restrict__ x64)
 {
-    const float dx = L.x - pj.x;
-    const float dy = L.y - pj.y;
-    const float dz = L.z - pj.z;
+    const float dx = pdiff<PER>(L.x, pj.x);
+    const float dy = pdiff<PER>(L.y, pj.y);
+    const float dz = pdiff<PER>(L.z, pj.z);
     const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
     const bool nr = r2 < thr2;
     float rinv = __builtin_amdgcn_rsqf(r2);
@@ -169,15 +216,7 @@ __device__ __forceinline__ void pair_f32(LaneF32& L, const float4 pj, const floa
     if (nr) {
         if (jg != L.i && L.i < n && jg < n) {
             double d0, d1, d2;
-            if (x64) {
-                d0 = x64[3 * (size_t)L.i + 0] - x64[3 * (size_t)jg + 0];
-                d1 = x64[3 * (size_t)L.i + 1] - x64[3 * (size_t)jg + 1];
-                d2 = x64[3 * (size_t)L.i + 2] - x64[3 * (size_t)jg + 2];
-            } else {
-                d0 = (double)L.x - (double)pj.x;
-                d1 = (double)L.y - (double)pj.y;
-                d2 = (double)L.z - (double)pj.z;
-            }
+            near_diff<PER>(L, pj, jg, pc, x64, d0, d1, d2);
             near_term<TENSOR>(pc, d0, d1, d2, (double)fj.x, (double)fj.y, (double)fj.z, L.n0,
                               L.n1, L.n2);
         }
@@ -188,22 +227,14 @@ __device__ __forceinline__ void pair_f32(LaneF32& L, const float4 pj, const floa
 // i, accumulated into the lane's own LDS slot (only the owning lane ever
 // touches it, so no synchronisation is needed and the order is fixed).  The
 // self pair and padded slots contribute nothing.
-template <int TENSOR>
+template <int TENSOR, bool PER>
 __device__ __forceinline__ void near_pair_lds(const LaneF32& L, const float4 pj, const float4 fj,
                                            int jg, int n, const PairConst& pc,
                                            const double* __restrict__ x64, double* slot, int stride)
 {
     if (jg == L.i || L.i >= n || jg >= n) return;
     double d0, d1, d2;
-    if (x64) {
-        d0 = x64[3 * (size_t)L.i + 0] - x64[3 * (size_t)jg + 0];
-        d1 = x64[3 * (size_t)L.i + 1] - x64[3 * (size_t)jg + 1];
-        d2 = x64[3 * (size_t)L.i + 2] - x64[3 * (size_t)jg + 2];
-    } else {
-        d0 = (double)L.x - (double)pj.x;
-        d1 = (double)L.y - (double)pj.y;
-        d2 = (double)L.z - (double)pj.z;
-    }
+    near_diff<PER>(L, pj, jg, pc, x64, d0, d1, d2);
     double n0 = slot[0], n1 = slot[stride], n2 = slot[2 * stride];
     near_term<TENSOR>(pc, d0, d1, d2, (double)fj.x, (double)fj.y, (double)fj.z, n0, n1, n2);
     slot[0] = n0;
@@ -219,7 +250,7 @@ __device__ __forceinline__ void near_pair_lds(const LaneF32& L, const float4 pj,
 // the same for every group.
 // ACC: 0 = plain FP32 sums, k >= 1 = Kahan compensation applied once per k
 // consecutive terms (k = 1: per term).
-template <int TENSOR, int ACC, int U, int ILP>
+template <int TENSOR, int ACC, int U, int ILP, bool PER>
 __device__ __forceinline__ void pair_group(LaneF32 (&L)[ILP], const float4 (&pj)[U],
                                            const float4 (&fj)[U], int jg0, int n,
                                            const PairConst& pc, float gamma, float m3g,
@@ -232,9 +263,9 @@ __device__ __forceinline__ void pair_group(LaneF32 (&L)[ILP], const float4 (&pj)
     for (int q = 0; q < ILP; ++q)
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            dx[q][u] = L[q].x - pj[u].x;
-            dy[q][u] = L[q].y - pj[u].y;
-            dz[q][u] = L[q].z - pj[u].z;
+            dx[q][u] = pdiff<PER>(L[q].x, pj[u].x);
+            dy[q][u] = pdiff<PER>(L[q].y, pj[u].y);
+            dz[q][u] = pdiff<PER>(L[q].z, pj[u].z);
             r2[q][u] = fmaf(dx[q][u], dx[q][u], fmaf(dy[q][u], dy[q][u], dz[q][u] * dz[q][u]));
             rmin = fminf(rmin, r2[q][u]);
         }
@@ -244,7 +275,7 @@ __device__ __forceinline__ void pair_group(LaneF32 (&L)[ILP], const float4 (&pj)
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 if (r2[q][u] < thr2)
-                    near_pair_lds<TENSOR>(L[q], pj[u], fj[u], jg0 + u, n, pc, x64,
+                    near_pair_lds<TENSOR, PER>(L[q], pj[u], fj[u], jg0 + u, n, pc, x64,
                                           near_slot + q * (stride / ILP), stride);
                 r2[q][u] = (r2[q][u] < thr2) ? __builtin_inff() : r2[q][u];
             }
@@ -295,7 +326,7 @@ __device__ __forceinline__ void pair_group(LaneF32 (&L)[ILP], const float4 (&pj)
     }
 }
 
-template <int ILP, int BLOCK>
+template <int ILP, int BLOCK, bool PER>
 __device__ __forceinline__ void lanes_init(LaneF32 (&L)[ILP], const float4* __restrict__ pos, int n,
                                            int ib)
 {
@@ -310,7 +341,7 @@ __device__ __forceinline__ void lanes_init(LaneF32 (&L)[ILP], const float4* __re
             L[q].y = p.y;
             L[q].z = p.z;
         } else {
-            L[q].x = L[q].y = L[q].z = SD_FAR_I;
+            L[q].x = L[q].y = L[q].z = far_i<PER>();
         }
         L[q].s0 = L[q].s1 = L[q].s2 = 0.0f;
         L[q].c0 = L[q].c1 = L[q].c2 = 0.0f;
@@ -359,7 +390,7 @@ struct GroupSize {
 // force, 32 B each) in LDS with coalesced 16-byte loads; the next tile is
 // fetched into registers while the current one is consumed.  Every lane then
 // reads each j from LDS by broadcast.
-template <int TENSOR, int ACC, int BLOCK, int ILP>
+template <int TENSOR, int ACC, int BLOCK, int ILP, bool PER>
 __global__ void __launch_bounds__(BLOCK)
 k_pair_f32_lds(const float4* __restrict__ pos, const float4* __restrict__ frc,
                const double* __restrict__ x64, int n, int jchunk, int S, PairConst pc,
@@ -371,7 +402,7 @@ k_pair_f32_lds(const float4* __restrict__ pos, const float4* __restrict__ frc,
     int ib, s;
     map_block(S, ib, s);
     LaneF32 L[ILP];
-    lanes_init<ILP, BLOCK>(L, pos, n, ib);
+    lanes_init<ILP, BLOCK, PER>(L, pos, n, ib);
     double* near_slot = near_slots_init<ILP, BLOCK>(s_near);
     constexpr int NS = BLOCK * ILP;
     constexpr int GROUP_U = GroupSize<ACC>::value;
@@ -379,10 +410,10 @@ k_pair_f32_lds(const float4* __restrict__ pos, const float4* __restrict__ frc,
     const int jbeg = s * jchunk;
     const int jend = min(n, jbeg + jchunk);
     const float gamma = pc.gamma_f, m3g = pc.m3gamma_f, thr2 = pc.thr2_f;
-    const float4 far_j = make_float4(SD_FAR_J, SD_FAR_J, SD_FAR_J, 0.0f);
+    const float4 far_j4 = make_float4(far_j<PER>(), far_j<PER>(), far_j<PER>(), 0.0f);
     const float4 zero4 = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
 
-    float4 rp = far_j, rf = zero4;
+    float4 rp = far_j4, rf = zero4;
     if (jbeg + tid < jend) {
         rp = pos[jbeg + tid];
         rf = frc[jbeg + tid];
@@ -393,7 +424,7 @@ k_pair_f32_lds(const float4* __restrict__ pos, const float4* __restrict__ frc,
         s_frc[tid] = rf;
         __syncthreads();
         const int jn = jt + BLOCK + tid;
-        rp = far_j;
+        rp = far_j4;
         rf = zero4;
         if (jn < jend) {
             rp = pos[jn];
@@ -406,18 +437,18 @@ k_pair_f32_lds(const float4* __restrict__ pos, const float4* __restrict__ frc,
                 pj[u] = s_pos[k + u];
                 fj[u] = s_frc[k + u];
             }
-            pair_group<TENSOR, ACC, GROUP_U, ILP>(L, pj, fj, jt + k, n, pc, gamma, m3g, thr2,
-                                                  x64, near_slot, NS);
+            pair_group<TENSOR, ACC, GROUP_U, ILP, PER>(L, pj, fj, jt + k, n, pc, gamma, m3g, thr2,
+                                                       x64, near_slot, NS);
         }
     }
-    lanes_store<ILP>(L, n, s, pc.alpha, near_slot, NS, partial);
+    lanes_store<ILP>(L, n, s, pc.alpha_sum, near_slot, NS, partial);
 }
 
 // Variant 1: no LDS.  The j index is wave-uniform, so positions and forces of
 // j are fetched with scalar loads through the scalar cache (the paper's
 // "naive" cache-based read of Sec. 3.2, on AMD's scalar path) and enter the
 // VALU as SGPR operands.
-template <int TENSOR, int ACC, int BLOCK, int ILP>
+template <int TENSOR, int ACC, int BLOCK, int ILP, bool PER>
 __global__ void __launch_bounds__(BLOCK)
 k_pair_f32_smem(const float4* __restrict__ pos, const float4* __restrict__ frc,
                 const double* __restrict__ x64, int n, int jchunk, int S, PairConst pc,
@@ -427,7 +458,7 @@ k_pair_f32_smem(const float4* __restrict__ pos, const float4* __restrict__ frc,
     int ib, s;
     map_block(S, ib, s);
     LaneF32 L[ILP];
-    lanes_init<ILP, BLOCK>(L, pos, n, ib);
+    lanes_init<ILP, BLOCK, PER>(L, pos, n, ib);
     double* near_slot = near_slots_init<ILP, BLOCK>(s_near);
     constexpr int NS = BLOCK * ILP;
     constexpr int GROUP_U = GroupSize<ACC>::value;
@@ -442,22 +473,22 @@ k_pair_f32_smem(const float4* __restrict__ pos, const float4* __restrict__ frc,
             pj[u] = pos[j + u];
             fj[u] = frc[j + u];
         }
-        pair_group<TENSOR, ACC, GROUP_U, ILP>(L, pj, fj, j, n, pc, gamma, m3g, thr2, x64,
-                                              near_slot, NS);
+        pair_group<TENSOR, ACC, GROUP_U, ILP, PER>(L, pj, fj, j, n, pc, gamma, m3g, thr2, x64,
+                                                   near_slot, NS);
     }
     for (; j < jend; ++j) {
         const float4 pj = pos[j];
         const float4 fj = frc[j];
 #pragma unroll
         for (int q = 0; q < ILP; ++q)
-            pair_f32<TENSOR, ACC != 0>(L[q], pj, fj, j, n, pc, gamma, m3g, thr2, x64);
+            pair_f32<TENSOR, ACC != 0, PER>(L[q], pj, fj, j, n, pc, gamma, m3g, thr2, x64);
     }
-    lanes_store<ILP>(L, n, s, pc.alpha, near_slot, NS, partial);
+    lanes_store<ILP>(L, n, s, pc.alpha_sum, near_slot, NS, partial);
 }
 
 // ---------------------------------------------------------------- FP64 path
 
-template <int TENSOR, int BLOCK>
+template <int TENSOR, int BLOCK, bool PER>
 __global__ void __launch_bounds__(BLOCK)
 k_pair_f64_lds(const double4* __restrict__ pos, const double4* __restrict__ frc, int n, int jchunk,
                int S, PairConst pc, double* __restrict__ partial)
@@ -502,7 +533,12 @@ k_pair_f64_lds(const double4* __restrict__ pos, const double4* __restrict__ frc,
         for (int k = 0; k < BLOCK; ++k) {
             const double4 pj = s_pos[k];
             const double4 fj = s_frc[k];
-            const double dx = xi0 - pj.x, dy = xi1 - pj.y, dz = xi2 - pj.z;
+            double dx = xi0 - pj.x, dy = xi1 - pj.y, dz = xi2 - pj.z;
+            if (PER) {  // nearest image; an exact half-box difference may take either image
+                dx = fma(-pc.box, rint(dx * pc.ibox), dx);
+                dy = fma(-pc.box, rint(dy * pc.ibox), dy);
+                dz = fma(-pc.box, rint(dz * pc.ibox), dz);
+            }
             const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
             const bool nr = r2 < thr2;
             double rinv = rsqrt(r2);
@@ -563,12 +599,21 @@ static hipError_t launch_f32_t(const PairLaunch& L, const float4* pos, const flo
 {
     const int iblocks = (n + BLOCK * ILP - 1) / (BLOCK * ILP);
     dim3 grid(iblocks * L.splits), block(BLOCK);
-    if (L.variant == 1)
-        hipLaunchKernelGGL((k_pair_f32_smem<TENSOR, ACC, BLOCK, ILP>), grid, block, 0, st, pos,
-                           frc, x64, n, L.jchunk, L.splits, pc, partial);
-    else
-        hipLaunchKernelGGL((k_pair_f32_lds<TENSOR, ACC, BLOCK, ILP>), grid, block, 0, st, pos,
-                           frc, x64, n, L.jchunk, L.splits, pc, partial);
+    if (pc.box > 0.0) {
+        if (L.variant == 1)
+            hipLaunchKernelGGL((k_pair_f32_smem<TENSOR, ACC, BLOCK, ILP, true>), grid, block, 0,
+                               st, pos, frc, x64, n, L.jchunk, L.splits, pc, partial);
+        else
+            hipLaunchKernelGGL((k_pair_f32_lds<TENSOR, ACC, BLOCK, ILP, true>), grid, block, 0,
+                               st, pos, frc, x64, n, L.jchunk, L.splits, pc, partial);
+    } else {
+        if (L.variant == 1)
+            hipLaunchKernelGGL((k_pair_f32_smem<TENSOR, ACC, BLOCK, ILP, false>), grid, block, 0,
+                               st, pos, frc, x64, n, L.jchunk, L.splits, pc, partial);
+        else
+            hipLaunchKernelGGL((k_pair_f32_lds<TENSOR, ACC, BLOCK, ILP, false>), grid, block, 0,
+                               st, pos, frc, x64, n, L.jchunk, L.splits, pc, partial);
+    }
     return hipGetLastError();
 }
 
@@ -609,8 +654,12 @@ static hipError_t launch_f64_t(const PairLaunch& L, const double4* pos, const do
                                const PairConst& pc, double* partial, hipStream_t st)
 {
     dim3 grid(((n + BLOCK - 1) / BLOCK) * L.splits), block(BLOCK);
-    hipLaunchKernelGGL((k_pair_f64_lds<TENSOR, BLOCK>), grid, block, 0, st, pos, frc, n, L.jchunk,
-                       L.splits, pc, partial);
+    if (pc.box > 0.0)
+        hipLaunchKernelGGL((k_pair_f64_lds<TENSOR, BLOCK, true>), grid, block, 0, st, pos, frc, n,
+                           L.jchunk, L.splits, pc, partial);
+    else
+        hipLaunchKernelGGL((k_pair_f64_lds<TENSOR, BLOCK, false>), grid, block, 0, st, pos, frc,
+                           n, L.jchunk, L.splits, pc, partial);
     return hipGetLastError();
 }
 

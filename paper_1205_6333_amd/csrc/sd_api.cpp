@@ -47,6 +47,21 @@ sd_status check_params(const sd_params* p)
     if (p->tensor != SD_RPY && p->tensor != SD_OSEEN) return fail(SD_EINVAL, "unknown tensor");
     if (p->overlap != SD_OVERLAP_NONE && p->overlap != SD_OVERLAP_RPY)
         return fail(SD_EINVAL, "unknown overlap mode");
+    for (int k = 0; k < 3; ++k)
+        if (!(p->box[k] >= 0.0) || !std::isfinite(p->box[k]))
+            return fail(SD_EINVAL, "box sides must be finite and >= 0");
+    if (p->box[0] != 0.0 || p->box[1] != 0.0 || p->box[2] != 0.0) {
+        if (p->box[0] != p->box[1] || p->box[0] != p->box[2])
+            return fail(SD_EUNSUPPORTED, "the box must be cubic (three equal sides) or absent");
+        if (!(p->box[0] > 2.0 * p->a))
+            return fail(SD_EINVAL, "the box side must exceed the sphere diameter 2a");
+    }
+    return SD_OK;
+}
+
+sd_status check_free_space(const sd_params* p, const char* what)
+{
+    if (box_side(p) > 0.0) return fail(SD_EUNSUPPORTED, "%s does not support a periodic box", what);
     return SD_OK;
 }
 
@@ -285,7 +300,7 @@ static void prof_end(hipStream_t st, hipEvent_t a)
 
 PairConst pair_const(const sd_params* p)
 {
-    return make_pair_const(p->a, p->eta, p->tensor, p->overlap);
+    return make_pair_const(p->a, p->eta, p->tensor, p->overlap, box_side(p));
 }
 
 // Launch the pair kernel for n particles; returns the number of splits used
@@ -344,7 +359,16 @@ sd_status mobility_apply(const sd_params* p, int64_t n, const void* pos, const v
     const PairLaunch L = plan_pair(precision, n);
     void* partial = nullptr;
     if ((st = ws_get(WS_PARTIAL, partial_bytes(L, n), &partial))) return st;
-    if ((st = run_pair(p, n, pos, force, nullptr, precision, (double*)partial, L, hs))) return st;
+    const void* pos_k = pos;
+    if (box_side(p) > 0.0 && precision != SD_FP64) {  // fixed-point records for the box
+        void* q = nullptr;
+        if ((st = ws_get(WS_QPOS, (size_t)n * 16, &q))) return st;
+        hipError_t e = launch_stage_q_from_f32((const float4*)pos, (float4*)q, (int)n,
+                                               box_side(p), hs);
+        if (e != hipSuccess) return fail(SD_EDEVICE, "stage launch: %s", hipGetErrorString(e));
+        pos_k = q;
+    }
+    if ((st = run_pair(p, n, pos_k, force, nullptr, precision, (double*)partial, L, hs))) return st;
     hipError_t e = (precision == SD_FP64)
                        ? launch_merge_f64((double*)partial, L.splits, (int)n, (const double4*)force,
                                           1.0 / (6.0 * M_PI * p->eta * p->a), vel, hs)
@@ -365,7 +389,7 @@ static sd_status step_impl(const sd_params* p, int64_t n, double* x, const void*
     hipError_t e;
     if (!staged) {
         e = (prec == SD_FP64) ? launch_stage_f64(x, (double4*)pos_stage, (int)n, hs)
-                              : launch_stage_f32(x, (float4*)pos_stage, (int)n, hs);
+                              : launch_stage_f32(x, (float4*)pos_stage, (int)n, box_side(p), hs);
         if (e != hipSuccess) return fail(SD_EDEVICE, "stage launch: %s", hipGetErrorString(e));
     }
     if ((st = run_pair(p, n, pos_stage, force, prec == SD_FP64 ? nullptr : x, prec, partial, L,
@@ -380,7 +404,7 @@ static sd_status step_impl(const sd_params* p, int64_t n, double* x, const void*
     else
         e = launch_merge_integrate_f32(partial, L.splits, (int)n, (const float4*)force, mu0, x,
                                        v_prev, v_out, dt, mode,
-                                       stage_next ? (float4*)pos_stage : nullptr, hs);
+                                       stage_next ? (float4*)pos_stage : nullptr, box_side(p), hs);
     if (e != hipSuccess) return fail(SD_EDEVICE, "integrate launch: %s", hipGetErrorString(e));
     return SD_OK;
 }

@@ -22,12 +22,17 @@ enum {
     WS_TUNE,          // autotuner scratch
     WS_LUB,           // lubrication cell list
     WS_LUB_F,         // lubrication-corrected forces of a step
+    WS_QPOS,          // fixed-point positions of a product in a periodic box
     WS_COUNT
 };
 
 sd_status fail(sd_status st, const char* fmt, ...);
 sd_status check_lub(const sd_lub* lub);
 sd_status check_params(const sd_params* p);
+// cubic box side of validated params (0 = free space)
+inline double box_side(const sd_params* p) { return p->box[0]; }
+// SD_EUNSUPPORTED for a periodic box (entry points without box support)
+sd_status check_free_space(const sd_params* p, const char* what);
 sd_status check_n(int64_t n);
 sd_status check_precision(int32_t prec);
 sd_status check_ptr(const void* ptr, size_t align, const char* name);

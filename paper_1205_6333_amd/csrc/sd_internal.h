@@ -21,23 +21,48 @@ enum { T_RPY = 0, T_OSEEN = 1 };
 // alpha is taken once per particle, in FP64.  Pairs with r^2 < thr2 (near
 // contact, overlap, coincidence, self) skip the fast path and are evaluated in
 // FP64 from the same definitions.
+//
+// Periodic cubic box of side Lb (nearest image, footnote of Sec. 3.1): the
+// FP32 path stages positions as 32-bit fixed-point fractions of the box,
+// q = x 2^32 / Lb mod 2^32, so that the wrapped integer difference
+// q_i - q_j (two's complement) is exactly the nearest-image difference in
+// units of s = Lb / 2^32 (a difference of exactly Lb/2 becomes -Lb/2).  With
+// d = s e the pair term is (alpha / s) [A'(e; gamma/s^2) F + Bt'(e; gamma/s^2)
+// (e.F) e], so the FP32 constants below are the scaled ones and the scale is
+// folded into alpha_sum.  The FP64 path folds d -= Lb rint(d / Lb).
 struct PairConst {
-    float gamma_f;       // 2a^2/3 (RPY) or 0 (Oseen)
-    float m3gamma_f;     // -3 gamma
-    float thr2_f;        // near threshold on r^2, FP32
+    float gamma_f;       // 2a^2/3 (RPY) or 0 (Oseen); / s^2 when periodic
+    float m3gamma_f;     // -3 gamma_f
+    float thr2_f;        // near threshold on r^2, FP32 (/ s^2 when periodic)
     int overlap;         // 1: overlap form for r < 2a (RPY only)
-    double thr2_d;       // near threshold on r^2, FP64
+    double thr2_d;       // near threshold on r^2, FP64 (physical units)
     double alpha;        // 1/(8 pi eta)
+    double alpha_sum;    // factor of the FP32 sums: alpha, or alpha / s when periodic
     double gamma;        // 2a^2/3 (RPY) or 0 (Oseen)
     double mu0;          // 1/(6 pi eta a)
     double a;
+    double box;          // cubic box side Lb, 0 = free space
+    double ibox;         // 1 / Lb (0 in free space)
+    double s_q;          // fixed-point unit Lb / 2^32 (0 in free space)
 };
+
+// Nearest image of a difference vector, FP64 (round-half-even of d / Lb).
+__host__ __device__ inline void nearest_image_d(const PairConst& pc, double& d0, double& d1,
+                                                double& d2)
+{
+    if (pc.box > 0.0) {
+        d0 -= pc.box * rint(d0 / pc.box);
+        d1 -= pc.box * rint(d1 / pc.box);
+        d2 -= pc.box * rint(d2 / pc.box);
+    }
+}
 
 // Relative widening of the near threshold: pairs with r^2 < (2a)^2 (1 + NEAR_EPS)
 // are evaluated in FP64.
 constexpr double NEAR_EPS = 1e-3;
 
-PairConst make_pair_const(double a, double eta, int tensor, int overlap);
+// box: cubic box side (0 = free space).
+PairConst make_pair_const(double a, double eta, int tensor, int overlap, double box);
 
 struct PairLaunch {
     int variant;   // 0 LDS tiles, 1 scalar-cache j stream
@@ -54,6 +79,8 @@ PairLaunch shape_pair_launch(int n, int variant, int block, int splits, int ilp)
 // Pair kernels: partial[(s*3 + k)*n + i] = sum over split s of the pair terms
 // (self excluded), FP64 output.
 // x64 (f64[3n], may be null): FP64 positions used for near pairs.
+// With pc.box > 0 the FP32 kernel reads fixed-point positions (uint4 bits in
+// the float4 records, see PairConst) and the FP64 kernel folds differences.
 hipError_t launch_pair_f32(const PairLaunch& L, int tensor, int acc, const float4* pos,
                            const float4* frc, const double* x64, int n, const PairConst& pc,
                            double* partial, hipStream_t st);
@@ -66,13 +93,18 @@ hipError_t launch_merge_f32(const double* partial, int splits, int n, const floa
 hipError_t launch_merge_f64(const double* partial, int splits, int n, const double4* frc,
                             double mu0, double* vel, hipStream_t st);
 
-// Time loop helpers.
-hipError_t launch_stage_f32(const double* x, float4* pos, int n, hipStream_t st);
+// Time loop helpers.  box > 0: the FP32 stage is the fixed-point form of a
+// periodic box of that side (see PairConst); the FP64 stage is unchanged.
+hipError_t launch_stage_f32(const double* x, float4* pos, int n, double box, hipStream_t st);
 hipError_t launch_stage_f64(const double* x, double4* pos, int n, hipStream_t st);
+// fixed-point form of FP32 position records (mobility product in a box)
+hipError_t launch_stage_q_from_f32(const float4* pos, float4* q, int n, double box,
+                                   hipStream_t st);
 // mode: 0 Euler, 1 AB2 start (Euler + store v_prev), 2 AB2
 hipError_t launch_merge_integrate_f32(const double* partial, int splits, int n, const float4* frc,
                                       double mu0, double* x, double* v_prev, double* v_out,
-                                      double dt, int mode, float4* pos_next, hipStream_t st);
+                                      double dt, int mode, float4* pos_next, double box,
+                                      hipStream_t st);
 hipError_t launch_merge_integrate_f64(const double* partial, int splits, int n, const double4* frc,
                                       double mu0, double* x, double* v_prev, double* v_out,
                                       double dt, int mode, double4* pos_next, hipStream_t st);

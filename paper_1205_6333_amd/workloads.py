@@ -37,10 +37,13 @@ def box_side(n: int, phi: float, a: float = 1.0) -> float:
     return float((n * 4.0 * np.pi * a ** 3 / 3.0 / phi) ** (1.0 / 3.0))
 
 
-def _sequential_reject(draw, n: int, min_dist: float, batch: int = 8192) -> np.ndarray:
+def _sequential_reject(draw, n: int, min_dist: float, batch: int = 8192,
+                       boxsize: float | None = None) -> np.ndarray:
     """Accept candidates from ``draw(k) -> (k, 3)`` in stream order; a candidate
     is rejected when its distance to an already accepted one is < min_dist.
-    Exactly the one-at-a-time procedure, evaluated batch-wise."""
+    Exactly the one-at-a-time procedure, evaluated batch-wise.  ``boxsize``:
+    distances are nearest-image distances of that periodic cube (candidates
+    must lie in [0, boxsize))."""
     acc = np.empty((n, 3))
     count = 0
     while count < n:
@@ -48,24 +51,26 @@ def _sequential_reject(draw, n: int, min_dist: float, batch: int = 8192) -> np.n
         ok = np.ones(len(cand), dtype=bool)
         if count:
             if cKDTree is not None:
-                d, _ = cKDTree(acc[:count]).query(cand, k=1)
+                d, _ = cKDTree(acc[:count], boxsize=boxsize).query(cand, k=1)
             else:
-                d = np.sqrt(((cand[:, None, :] - acc[None, :count, :]) ** 2).sum(-1)).min(1)
+                d = np.sqrt((_img(cand[:, None, :] - acc[None, :count, :], boxsize) ** 2)
+                            .sum(-1)).min(1)
             ok &= d >= min_dist
         idx = np.nonzero(ok)[0]
         c2 = cand[idx]
         keep = np.ones(len(c2), dtype=bool)
         if len(c2) > 1:
             if cKDTree is not None:
-                pairs = cKDTree(c2).query_pairs(min_dist * (1 - 1e-15), output_type="ndarray")
+                pairs = cKDTree(c2, boxsize=boxsize).query_pairs(min_dist * (1 - 1e-15),
+                                                                 output_type="ndarray")
             else:
-                dd = np.sqrt(((c2[:, None, :] - c2[None, :, :]) ** 2).sum(-1))
+                dd = np.sqrt((_img(c2[:, None, :] - c2[None, :, :], boxsize) ** 2).sum(-1))
                 ii, jj = np.nonzero(np.triu(dd < min_dist, 1))
                 pairs = np.stack([ii, jj], 1)
             if len(pairs):
                 pairs = np.sort(pairs, axis=1)
                 # exact check of the boundary (query_pairs uses <=)
-                dd = np.sqrt(((c2[pairs[:, 0]] - c2[pairs[:, 1]]) ** 2).sum(-1))
+                dd = np.sqrt((_img(c2[pairs[:, 0]] - c2[pairs[:, 1]], boxsize) ** 2).sum(-1))
                 pairs = pairs[dd < min_dist]
                 earlier = {}
                 for i, j in pairs:
@@ -80,6 +85,12 @@ def _sequential_reject(draw, n: int, min_dist: float, batch: int = 8192) -> np.n
     return acc
 
 
+def _img(d, boxsize):
+    """Nearest-image difference in a periodic cube (identity without a box);
+    used only to measure distances for the rejection test."""
+    return d if boxsize is None else d - boxsize * np.rint(d / boxsize)
+
+
 def random_suspension(n: int, phi: float = 0.05, a: float = 1.0, min_dist: float = 2.2,
                       seed: int = 1) -> np.ndarray:
     """(n, 3) float64 positions: random sequential addition in a centred cube."""
@@ -87,6 +98,17 @@ def random_suspension(n: int, phi: float = 0.05, a: float = 1.0, min_dist: float
     rng = np.random.default_rng(seed)
     return _sequential_reject(lambda k: rng.uniform(-L / 2, L / 2, size=(k, 3)), n,
                               min_dist * a)
+
+
+def periodic_suspension(n: int, phi: float = 0.05, a: float = 1.0, min_dist: float = 2.2,
+                        seed: int = 1):
+    """Random sequential addition in a periodic cube [0, L)^3 (nearest-image
+    distances in the rejection test).  Returns (positions (n, 3), L)."""
+    L = box_side(n, phi, a)
+    rng = np.random.default_rng(seed)
+    x = _sequential_reject(lambda k: rng.uniform(0.0, L, size=(k, 3)), n, min_dist * a,
+                           boxsize=L)
+    return x, L
 
 
 def gaussian_forces(n: int, seed: int = 2) -> np.ndarray:
@@ -162,6 +184,16 @@ def fcc_lattice(m: int, density: float = 0.1, a: float = 1.0):
     cells = np.stack(np.meshgrid(g, g, g, indexing="ij"), -1).reshape(-1, 3)
     x = (cells[:, None, :] + basis[None, :, :]).reshape(-1, 3) * c
     return x, m * c
+
+
+def jittered_fcc(m: int, density: float = 0.1, a: float = 1.0, jitter: float = 0.05,
+                 seed: int = 4):
+    """The fcc start of ``fcc_lattice`` with every coordinate displaced by
+    U(-jitter, jitter) a and wrapped into [0, L): no pair is exactly half a box
+    apart, so the nearest image of every pair is unique.  Returns (x, L)."""
+    x, L = fcc_lattice(m, density, a)
+    x = x + np.random.default_rng(seed).uniform(-jitter * a, jitter * a, size=x.shape)
+    return x - L * np.floor(x / L), L
 
 
 def to_float4(v: np.ndarray, dtype=np.float32) -> np.ndarray:

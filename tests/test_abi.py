@@ -114,3 +114,27 @@ def test_batch_plan_errors(L):
     assert L.sd_batch_create(ctypes.byref(p), 1, offs, ctypes.byref(h)) == b.SD_EINVAL
     assert L.sd_batch_create(ctypes.byref(p), 0, offs, ctypes.byref(h)) == b.SD_EINVAL
     assert L.sd_batch_create(ctypes.byref(p), 1, None, ctypes.byref(h)) == b.SD_EINVAL
+
+
+def test_periodic_box_validation(L):
+    """Box sides: finite, >= 0, cubic when set, larger than one sphere; the
+    adjoint and batched entry points reject a box."""
+    from paper_1205_6333_amd import binding as b
+    vp = ctypes.c_void_p
+    ok16 = vp(1 << 20)
+    for box in ((-1.0, -1.0, -1.0), (float("nan"),) * 3, (float("inf"),) * 3, (1.5, 1.5, 1.5)):
+        p = b.params(a=1.0, box=box)
+        assert L.mobility_apply(ctypes.byref(p), 5, ok16, ok16, ok16, 0, None) == b.SD_EINVAL
+    for box in ((10.0, 10.0, 12.0), (10.0, 0.0, 10.0)):
+        p = b.params(box=box)
+        assert L.mobility_apply(ctypes.byref(p), 5, ok16, ok16, ok16, 0, None) == b.SD_EUNSUPPORTED
+    p = b.params(box=20.0)
+    assert tuple(p.box) == (20.0, 20.0, 20.0)
+    assert L.mobility_adjoint(ctypes.byref(p), 5, ok16, ok16, ok16, ok16, ok16, 0,
+                              None) == b.SD_EUNSUPPORTED
+    assert L.sd_run_adjoint(ctypes.byref(p), 5, ok16, ok16, 0.1, 3, 0, None, 1, ok16, ok16, ok16,
+                            None) == b.SD_EUNSUPPORTED
+    h = ctypes.c_void_p()
+    offs = (ctypes.c_int64 * 2)(0, 5)
+    assert L.sd_batch_create(ctypes.byref(p), 1, offs, ctypes.byref(h)) == b.SD_EUNSUPPORTED
+    assert b"periodic box" in L.sd_last_error()
