@@ -26,6 +26,11 @@ Other rows of the hot path are measured with --workload (one JSON line each):
             checkpoint every 20 steps: forward and backward times
   lubrication  N = 65536 suspension, lubrication correction (Eq. 8) with the
             previous velocities, Euler dt = 0.001 (--loop-steps steps)
+  fcc       the benchmark of Sec. 3.3: sedimentation F = (0, 0, -1) from a
+            perfect fcc lattice at n = 0.1/a^3 in a periodic cube (nearest
+            image), Euler dt = 0.001, 100 steps, N = 4 m^3 from 256 to 202612:
+            runtime per step with and without the lubrication correction, and
+            the FP64 path
   copy      a plain device copy of --copy-mib MiB (calibrates HBM counters)
 """
 from __future__ import annotations
@@ -267,6 +272,54 @@ def run_lubrication(args, sd, W, dev):
                                    "dt=0.001, %d steps" % (n, steps)}}
 
 
+FCC_M = (4, 6, 8, 11, 16, 20, 25, 32, 37)   # N = 4 m^3 = 256 ... 202612
+
+
+def run_fcc(args, sd, W, dev):
+    import torch
+    steps, dt = 100, 0.001
+    rows = []
+    for m in FCC_M:
+        x0, L = W.fcc_lattice(m, density=0.1)
+        n = len(x0)
+        f = W.gravity_forces(n)
+        p = sd.params(box=L)
+        fd = torch.tensor(f, device=dev)
+        f4 = _to4(f, torch.float32, dev)
+        f4d = _to4(f, torch.float64, dev)
+        x = torch.tensor(x0, device=dev)
+        vp = torch.zeros_like(x)
+        sd.sd_run_lub(x, fd, vp, dt, 3, params=p)          # warm-up
+        sd.sd_run(x, f4, dt, 3, params=p)
+        x.copy_(torch.tensor(x0, device=dev))
+        vp.zero_()
+        t_lub = _sync_time(lambda: sd.sd_run_lub(x, fd, vp, dt, steps, params=p))
+        vz = float(vp[:, 2].mean())
+        x.copy_(torch.tensor(x0, device=dev))
+        t_plain = _sync_time(lambda: sd.sd_run(x, f4, dt, steps, params=p))
+        s64 = steps if n <= 65536 else 10
+        x.copy_(torch.tensor(x0, device=dev))
+        sd.sd_run(x, f4d, dt, 1, params=p, precision=sd.SD_FP64)
+        t64 = _sync_time(lambda: sd.sd_run(x, f4d, dt, s64, params=p, precision=sd.SD_FP64))
+        row = {"m": m, "n": n, "box": L, "ms_per_step": t_lub * 1e3 / steps,
+               "ms_per_step_without_lubrication": t_plain * 1e3 / steps,
+               "ms_per_step_fp64_without_lubrication": t64 * 1e3 / s64,
+               "g_pairs_per_s": float(n) * n * steps / t_lub / 1e9,
+               "sedimentation_velocity": vz}
+        print("bench fcc: %s" % json.dumps(row), file=sys.stderr, flush=True)
+        rows.append(row)
+    big = rows[-1]
+    return {"metric": "ms per Euler step of the fcc sedimentation benchmark at N=%d "
+                      "(periodic box, lubrication, FP32-comp pair kernel)" % big["n"],
+            "value": big["ms_per_step"], "unit": "ms/step", "n_gpus": 1,
+            "higher_is_better": False, "dtype": "f32", "data": "synthetic", "steps": steps,
+            "ms_per_step": big["ms_per_step"], "table": rows,
+            "config": {"workload": "Sec. 3.3 benchmark: perfect fcc lattice, n=0.1/a^3, periodic "
+                                   "cube with nearest-image interactions, F=(0,0,-1), RPY, "
+                                   "lubrication s<1 with the previous velocities, Euler "
+                                   "dt=0.001, 100 steps, N=4m^3 for m in %s" % (FCC_M,)}}
+
+
 def run_copy(args, dev):
     import torch
     m = int(args.copy_mib * 2 ** 20 // 4)
@@ -291,7 +344,8 @@ def main():
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 GPU path")
     ap.add_argument("--tune", action="store_true", help="autotune the kernel shape first (untimed)")
     ap.add_argument("--workload", default="product",
-                    choices=["product", "timeloop", "batched", "adjoint", "lubrication", "copy"])
+                    choices=["product", "timeloop", "batched", "adjoint", "lubrication", "fcc",
+                             "copy"])
     ap.add_argument("--loop-steps", type=int, default=1000, help="steps of --workload timeloop")
     ap.add_argument("--copy-mib", type=float, default=256.0)
     args = ap.parse_args()
@@ -311,6 +365,7 @@ def main():
               "batched": lambda: run_batched(args, sd, W, dev),
               "adjoint": lambda: run_adjoint(args, sd, W, dev),
               "lubrication": lambda: run_lubrication(args, sd, W, dev),
+              "fcc": lambda: run_fcc(args, sd, W, dev),
               "copy": lambda: run_copy(args, dev)}[args.workload]
         print(json.dumps(fn()))
         return 0
