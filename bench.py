@@ -31,6 +31,11 @@ Other rows of the hot path are measured with --workload (one JSON line each):
             image), Euler dt = 0.001, 100 steps, N = 4 m^3 from 256 to 202612:
             runtime per step with and without the lubrication correction, and
             the FP64 path
+  precision the numerical-stability study of Sec. 4: the four-sphere cluster
+            integrated for --study-time tau_s with single / double-single
+            (and Kahan, FP64) accumulation of the hydrodynamic interactions
+            and positions, dt = 0.01 and 0.001, all runs in one launch per
+            chunk; cycle duration and amplitude by parabolic fits of x_1(t)
   copy      a plain device copy of --copy-mib MiB (calibrates HBM counters)
 """
 from __future__ import annotations
@@ -320,6 +325,72 @@ def run_fcc(args, sd, W, dev):
                                    "dt=0.001, 100 steps, N=4m^3 for m in %s" % (FCC_M,)}}
 
 
+ACC_NAMES = {0: "single", 1: "kahan", 2: "double-single", 3: "fp64"}
+POS_NAMES = {0: "single", 1: "double-single", 2: "fp64"}
+
+
+def run_precision(args, sd, W, dev):
+    import torch
+    from paper_1205_6333_amd import observables as OB
+    x0, f = W.four_sphere_tetrahedron()
+    grid = [(a, p) for a in (0, 2) for p in (0, 1)] + [(1, 2), (3, 2)]
+    runs = [(a, p, dt) for dt in (0.01, 0.001) for (a, p) in grid]
+    t_total = float(args.study_time)
+    chunk_t = min(2000.0, t_total)            # tau_s per call
+    sample_t = 0.5                             # frame spacing in tau_s
+    specs = []
+    for a, p, dt in runs:
+        steps = int(round(chunk_t / dt))
+        specs.append(dict(acc=a, pos=p, dt=dt, steps=steps, stride=int(round(sample_t / dt))))
+    state = torch.zeros((len(runs), 2, 4, 3), dtype=torch.float64, device=dev)
+    state[:, 0] = torch.tensor(x0, device=dev)
+    fd = torch.tensor(f, device=dev)
+    nf = [s["steps"] // s["stride"] for s in specs]
+    series = [[] for _ in runs]                # (x1, y1) frames per run
+    n_calls = int(np.ceil(t_total / chunk_t))
+    t_gpu = 0.0
+    for c in range(n_calls):
+        out = {}
+        t_gpu += _sync_time(lambda: out.update(traj=sd.sd_cluster_run(state, fd, specs)))
+        traj = out["traj"].cpu().numpy()
+        off = 0
+        for r, k in enumerate(nf):
+            series[r].append(traj[off:off + k, 0, :2].copy())
+            off += k
+        if c % 10 == 0 or c == n_calls - 1:
+            print("bench precision: %.0f of %.0f tau_s, %.1f s on the GPU" %
+                  ((c + 1) * chunk_t, n_calls * chunk_t, t_gpu), file=sys.stderr, flush=True)
+    rows = []
+    window = 1.0e4
+    for r, (a, p, dt) in enumerate(runs):
+        xy = np.concatenate(series[r])
+        t = sample_t * np.arange(1, len(xy) + 1)
+        tc, dur, ta, amp = OB.cycles(t, xy[:, 0])
+        row = {"hi_accumulation": ACC_NAMES[a], "positions": POS_NAMES[p], "dt": dt,
+               "cycles": int(len(dur)), "max_abs_y1": float(np.abs(xy[:, 1]).max())}
+        if len(dur):
+            first = dur[tc < tc[0] + window]
+            last = dur[tc > tc[-1] - window]
+            row.update({"period_first_window": float(first.mean()),
+                        "period_last_window": float(last.mean()),
+                        "period_min": float(dur.min()), "period_max": float(dur.max()),
+                        "amplitude_first": float(amp[0]) if len(amp) else None,
+                        "amplitude_last": float(amp[-1]) if len(amp) else None,
+                        "last_cycle_end": float(tc[-1] + 0.5 * dur[-1])})
+        rows.append(row)
+    steps_fine = int(round(n_calls * chunk_t / 0.001))
+    return {"metric": "Euler steps/s of one four-sphere run (precision study of Sec. 4, "
+                      "%d runs per launch)" % len(runs),
+            "value": steps_fine / t_gpu, "unit": "steps/s", "n_gpus": 1,
+            "higher_is_better": True, "dtype": "f32", "data": "synthetic",
+            "gpu_seconds": t_gpu, "simulated_tau_s": n_calls * chunk_t, "runs": rows,
+            "config": {"workload": "four sedimenting spheres (tetrahedron of Fig. 4), F=(0,0,-1), "
+                                   "RPY, mu0=a=1, Euler; HI accumulation x positions in "
+                                   "{single, double-single} plus (kahan, fp64) and (fp64, fp64); "
+                                   "dt in {0.01, 0.001}; x_1 sampled every 0.5 tau_s; periods "
+                                   "averaged over windows of 1e4 tau_s"}}
+
+
 def run_copy(args, dev):
     import torch
     m = int(args.copy_mib * 2 ** 20 // 4)
@@ -345,7 +416,9 @@ def main():
     ap.add_argument("--tune", action="store_true", help="autotune the kernel shape first (untimed)")
     ap.add_argument("--workload", default="product",
                     choices=["product", "timeloop", "batched", "adjoint", "lubrication", "fcc",
-                             "copy"])
+                             "precision", "copy"])
+    ap.add_argument("--study-time", type=float, default=2.0e4,
+                    help="simulated tau_s of --workload precision (the paper: 5e5)")
     ap.add_argument("--loop-steps", type=int, default=1000, help="steps of --workload timeloop")
     ap.add_argument("--copy-mib", type=float, default=256.0)
     args = ap.parse_args()
@@ -366,6 +439,7 @@ def main():
               "adjoint": lambda: run_adjoint(args, sd, W, dev),
               "lubrication": lambda: run_lubrication(args, sd, W, dev),
               "fcc": lambda: run_fcc(args, sd, W, dev),
+              "precision": lambda: run_precision(args, sd, W, dev),
               "copy": lambda: run_copy(args, dev)}[args.workload]
         print(json.dumps(fn()))
         return 0

@@ -252,6 +252,62 @@ sd_status mobility_apply_batched(sd_batch* b, const void* pos, const void* force
 sd_status sd_run_batched(sd_batch* b, double* x, const void* force, double dt, int64_t steps,
                          int32_t integrator, int32_t precision, int32_t use_graph, void* stream);
 
+/* ---------------------------------------------------------- precision study */
+
+/* Precision of the accumulation of the pair sum sum_{j != i} T(r_i - r_j) F_j
+ * (the "HI" of Sec. 4).  The first three evaluate pair terms in FP32 (near
+ * pairs, r^2 < (2a)^2 (1 + 1e-3), in FP64 as in mobility_apply). */
+typedef enum sd_acc_mode {
+    SD_ACC_FP32 = 0,      /* plain FP32 sum ("single") */
+    SD_ACC_KAHAN = 1,     /* FP32 sum with Kahan compensation per term */
+    SD_ACC_DS = 2,        /* double-single sum: error-free FP32 two-sum of the
+                             running (hi, lo) pair and each term */
+    SD_ACC_FP64 = 3       /* pair terms and sum in FP64 */
+} sd_acc_mode;
+
+/* Precision of the positions and of the Euler update x += dt v. */
+typedef enum sd_pos_mode {
+    SD_POS_FP32 = 0,      /* FP32 positions ("single") */
+    SD_POS_DS = 1,        /* double-single positions (hi, lo) in FP32 */
+    SD_POS_FP64 = 2
+} sd_pos_mode;
+
+/* One run of the study. */
+typedef struct sd_cluster_spec {
+    int32_t acc;          /* sd_acc_mode */
+    int32_t pos;          /* sd_pos_mode */
+    double dt;            /* Euler time step, > 0 */
+    int64_t steps;        /* steps of this call, >= 0 */
+    int64_t stride;       /* a frame every `stride` steps; 0 = none */
+} sd_cluster_spec;
+
+#define SD_CLUSTER_MAX_N 64
+#define SD_CLUSTER_MAX_RUNS 4096
+
+/*
+ * sd_cluster_run -- the numerical-stability study of Sec. 4: `runs`
+ * independent Euler integrations of one small free-space cluster of n spheres
+ * (n <= SD_CLUSTER_MAX_N, e.g. the four sedimenting spheres of Fig. 4), each
+ * with its own accumulation and position precision and time step, all in ONE
+ * kernel launch (one wave per run, one lane per sphere; every step stays in
+ * registers and LDS).
+ *   specs  HOST sd_cluster_spec[runs]
+ *   state  device f64[runs][2][3n], in/out: run r's position of sphere i is
+ *          state[r][0][i] + state[r][1][i] (row-major xyz); a call loads it
+ *          into the run's precision and stores it back exactly (FP32 and FP64
+ *          runs store lo = 0, double-single runs their (hi, lo) pair), so
+ *          consecutive calls continue one trajectory.  Initialise with
+ *          hi = x0, lo = 0.
+ *   force  device f64[3n], the constant force on each sphere (all runs)
+ *   traj   device f64, or NULL when every stride is 0: the frames of run 0,
+ *          then of run 1, ...; run r writes floor(steps_r / stride_r) frames
+ *          of 3n values, frame k being the positions after (k + 1) stride_r
+ *          steps of this call.
+ * The box of p must be zero (SD_EUNSUPPORTED otherwise).
+ */
+sd_status sd_cluster_run(const sd_params* p, int64_t n, int32_t runs, const sd_cluster_spec* specs,
+                         double* state, const double* force, double* traj, void* stream);
+
 /* ------------------------------------------------------------------- tuning */
 
 /* Kernel shape of the all-pairs product. */

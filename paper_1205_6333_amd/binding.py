@@ -23,6 +23,9 @@ SD_OVERLAP_NONE, SD_OVERLAP_RPY = 0, 1
 SD_FP32_KAHAN, SD_FP64, SD_FP32_PLAIN = 0, 1, 2
 SD_EULER, SD_AB2 = 0, 1
 SD_BATCH_MAX_CLUSTER = 1024
+SD_ACC_FP32, SD_ACC_KAHAN, SD_ACC_DS, SD_ACC_FP64 = 0, 1, 2, 3
+SD_POS_FP32, SD_POS_DS, SD_POS_FP64 = 0, 1, 2
+SD_CLUSTER_MAX_N, SD_CLUSTER_MAX_RUNS = 64, 4096
 
 
 class SdParams(ctypes.Structure):
@@ -33,6 +36,11 @@ class SdParams(ctypes.Structure):
 
 class SdLub(ctypes.Structure):
     _fields_ = [("s_cut", ctypes.c_double), ("s_min", ctypes.c_double)]
+
+
+class SdClusterSpec(ctypes.Structure):
+    _fields_ = [("acc", ctypes.c_int32), ("pos", ctypes.c_int32), ("dt", ctypes.c_double),
+                ("steps", ctypes.c_int64), ("stride", ctypes.c_int64)]
 
 
 def lub(s_cut: float = 1.0, s_min: float = 1e-3) -> SdLub:
@@ -88,6 +96,7 @@ def lib() -> ctypes.CDLL:
             "lubrication_forces": [P, ctypes.POINTER(SdLub), i64, dp, dp, dp, dp, vp],
             "sd_run_lub": [P, ctypes.POINTER(SdLub), i64, dp, dp, dp, d, i64, i64, i32, i32, vp],
             "sd_mean_vector": [i64, dp, dp, vp],
+            "sd_cluster_run": [P, i64, i32, ctypes.POINTER(SdClusterSpec), dp, dp, dp, vp],
             "sd_profile_enable": [i32],
             "sd_profile_read": [ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double)],
             "sd_profile_reset": [],
@@ -352,6 +361,39 @@ def sd_run_batched(batch: Batch, x, force, dt: float, steps: int, *, integrator:
     check(lib().sd_run_batched(batch._h, _ptr(x), _ptr(force), float(dt), int(steps),
                                int(integrator), prec, int(bool(use_graph)), _stream(stream)))
     return x
+
+
+def cluster_frames(specs) -> int:
+    """Frames sd_cluster_run writes for these specs (all runs)."""
+    return sum(int(s["steps"]) // int(s["stride"]) for s in specs if int(s.get("stride", 0)) > 0)
+
+
+def sd_cluster_run(state, force, specs, traj=None, *, params: SdParams = None, stream=None):
+    """Runs of the precision study of Sec. 4 (see sd.h).  state: (runs, 2, n, 3)
+    float64 CUDA tensor (hi, lo) in/out; force: (n, 3) float64; specs: list of
+    dicts with keys acc, pos, dt, steps, stride (default 0).  Returns traj, a
+    (frames, n, 3) float64 tensor holding the frames of run 0, then run 1, ...
+    (allocated when not given), or None when no run records frames."""
+    import torch
+    runs = len(specs)
+    n = force.shape[0]
+    if tuple(state.shape) != (runs, 2, n, 3) or state.dtype != torch.float64 or \
+            not state.is_cuda or not state.is_contiguous():
+        raise ValueError("state must be a contiguous CUDA float64 tensor of shape (runs, 2, n, 3)")
+    _vec3(force, n, "force")
+    arr = (SdClusterSpec * runs)()
+    for k, sp in enumerate(specs):
+        arr[k] = SdClusterSpec(int(sp["acc"]), int(sp["pos"]), float(sp["dt"]), int(sp["steps"]),
+                               int(sp.get("stride", 0)))
+    frames = cluster_frames(specs)
+    if frames and traj is None:
+        traj = torch.empty((frames, n, 3), dtype=torch.float64, device=force.device)
+    if traj is not None:
+        _vec3(traj, frames * n, "traj")
+    p = params if params is not None else globals()["params"]()
+    check(lib().sd_cluster_run(ctypes.byref(p), n, runs, arr, _ptr(state), _ptr(force),
+                               _ptr(traj), _stream(stream)))
+    return traj if frames else None
 
 
 def sd_pack(v, precision: int = SD_FP32_KAHAN, out=None, stream=None):

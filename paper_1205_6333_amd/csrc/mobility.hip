@@ -13,6 +13,7 @@
 // r^2 < (2a)^2 (1 + NEAR_EPS), the self pair and coincident spheres are
 // evaluated in FP64 on a rarely taken branch.  SD_FP64 runs the same loop in
 // double.
+#include "pair_terms.h"
 #include "sd_internal.h"
 
 #include <cmath>
@@ -96,40 +97,6 @@ __device__ __forceinline__ float pdiff(float a, float b)
 {
     if (PER) return (float)(int)(__float_as_uint(a) - __float_as_uint(b));
     return a - b;
-}
-
-// FP64 contribution of one near pair (d = x_i - x_j, r^2 below threshold) to v_i.
-template <int TENSOR>
-__device__ __forceinline__ void near_term(const PairConst& pc, double d0, double d1, double d2,
-                                          double f0, double f1, double f2, double& n0, double& n1,
-                                          double& n2)
-{
-    const double r2 = d0 * d0 + d1 * d1 + d2 * d2;
-    if (r2 == 0.0) {  // coincident distinct spheres: limit of the overlap form, else nothing
-        if (TENSOR == T_RPY && pc.overlap) {
-            n0 += pc.mu0 * f0;
-            n1 += pc.mu0 * f1;
-            n2 += pc.mu0 * f2;
-        }
-        return;
-    }
-    const double r = sqrt(r2);
-    double cI, cD;  // T = cI I + cD d d
-    if (TENSOR == T_OSEEN) {
-        cI = pc.alpha / r;
-        cD = cI / r2;
-    } else if (pc.overlap && r < 2.0 * pc.a) {
-        cI = pc.mu0 * (1.0 - 9.0 * r / (32.0 * pc.a));
-        cD = pc.mu0 * 3.0 / (32.0 * pc.a * r);
-    } else {
-        const double ri = 1.0 / r, ri2 = ri * ri, ri3 = ri * ri2;
-        cI = pc.alpha * (ri + pc.gamma * ri3);
-        cD = pc.alpha * ri3 * (1.0 - 3.0 * pc.gamma * ri2);
-    }
-    const double dF = d0 * f0 + d1 * f1 + d2 * f2;
-    n0 += cI * f0 + cD * dF * d0;
-    n1 += cI * f1 + cD * dF * d1;
-    n2 += cI * f2 + cD * dF * d2;
 }
 
 // Per-lane state of one particle i.

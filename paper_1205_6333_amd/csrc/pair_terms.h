@@ -1,0 +1,44 @@
+// pair_terms.h -- FP64 evaluation of one pair term T(d) F_j of Eq. (7a)
+// (tensors of Eq. 4 and Eq. 7b, overlap form for r < 2a), shared by the
+// kernels that evaluate near pairs or whole runs in FP64.
+#pragma once
+
+#include "sd_internal.h"
+
+namespace sd {
+
+// FP64 contribution of one near pair (d = x_i - x_j, r^2 below threshold) to v_i.
+template <int TENSOR>
+__device__ __forceinline__ void near_term(const PairConst& pc, double d0, double d1, double d2,
+                                          double f0, double f1, double f2, double& n0, double& n1,
+                                          double& n2)
+{
+    const double r2 = d0 * d0 + d1 * d1 + d2 * d2;
+    if (r2 == 0.0) {  // coincident distinct spheres: limit of the overlap form, else nothing
+        if (TENSOR == T_RPY && pc.overlap) {
+            n0 += pc.mu0 * f0;
+            n1 += pc.mu0 * f1;
+            n2 += pc.mu0 * f2;
+        }
+        return;
+    }
+    const double r = sqrt(r2);
+    double cI, cD;  // T = cI I + cD d d
+    if (TENSOR == T_OSEEN) {
+        cI = pc.alpha / r;
+        cD = cI / r2;
+    } else if (pc.overlap && r < 2.0 * pc.a) {
+        cI = pc.mu0 * (1.0 - 9.0 * r / (32.0 * pc.a));
+        cD = pc.mu0 * 3.0 / (32.0 * pc.a * r);
+    } else {
+        const double ri = 1.0 / r, ri2 = ri * ri, ri3 = ri * ri2;
+        cI = pc.alpha * (ri + pc.gamma * ri3);
+        cD = pc.alpha * ri3 * (1.0 - 3.0 * pc.gamma * ri2);
+    }
+    const double dF = d0 * f0 + d1 * f1 + d2 * f2;
+    n0 += cI * f0 + cD * dF * d0;
+    n1 += cI * f1 + cD * dF * d1;
+    n2 += cI * f2 + cD * dF * d2;
+}
+
+}  // namespace sd

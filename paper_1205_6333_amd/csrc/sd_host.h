@@ -23,6 +23,7 @@ enum {
     WS_LUB,           // lubrication cell list
     WS_LUB_F,         // lubrication-corrected forces of a step
     WS_QPOS,          // fixed-point positions of a product in a periodic box
+    WS_CLUSTER,       // run records of the precision study
     WS_COUNT
 };
 

@@ -138,3 +138,31 @@ def test_periodic_box_validation(L):
     offs = (ctypes.c_int64 * 2)(0, 5)
     assert L.sd_batch_create(ctypes.byref(p), 1, offs, ctypes.byref(h)) == b.SD_EUNSUPPORTED
     assert b"periodic box" in L.sd_last_error()
+
+
+def test_cluster_run_validation(L):
+    from paper_1205_6333_amd import binding as b
+    vp = ctypes.c_void_p
+    ok8 = vp(1 << 20)
+    p = b.params()
+
+    def call(specs, n=4, runs=None, state=ok8, force=ok8, traj=None, params=p):
+        arr = (b.SdClusterSpec * max(1, len(specs)))(*specs)
+        return L.sd_cluster_run(ctypes.byref(params), n, len(specs) if runs is None else runs,
+                                arr, state, force, traj, None)
+
+    good = b.SdClusterSpec(b.SD_ACC_KAHAN, b.SD_POS_DS, 0.01, 10, 0)
+    assert call([good], n=0) == b.SD_EINVAL
+    assert call([good], n=65) == b.SD_EINVAL
+    assert call([good], runs=0) == b.SD_EINVAL
+    assert call([b.SdClusterSpec(4, 0, 0.01, 10, 0)]) == b.SD_EINVAL
+    assert call([b.SdClusterSpec(0, 3, 0.01, 10, 0)]) == b.SD_EINVAL
+    assert call([b.SdClusterSpec(0, 0, 0.0, 10, 0)]) == b.SD_EINVAL
+    assert call([b.SdClusterSpec(0, 0, 0.01, -1, 0)]) == b.SD_EINVAL
+    assert call([b.SdClusterSpec(0, 0, 0.01, 10, -2)]) == b.SD_EINVAL
+    assert call([b.SdClusterSpec(0, 0, 0.01, 10, 5)], traj=None) == b.SD_EINVAL  # frames, no traj
+    assert call([good], state=None) == b.SD_EINVAL
+    assert call([good], state=vp((1 << 20) + 4)) == b.SD_EALIGN
+    assert call([good], params=b.params(box=30.0)) == b.SD_EUNSUPPORTED
+    assert b.cluster_frames([dict(acc=0, pos=0, dt=0.1, steps=10, stride=3),
+                             dict(acc=0, pos=0, dt=0.1, steps=10, stride=0)]) == 3

@@ -444,3 +444,22 @@ def test_adjoint_matches_finite_differences(orc):
                     out[i, k] = (loss(x0, ap) - loss(x0, am)) / (2 * h)
     for g, fd in ((gx, fdx), (gf, fdf)):
         assert np.linalg.norm(g - fd) <= 1e-6 * np.linalg.norm(fd)
+
+
+def test_parabolic_extrema_of_a_sinusoid():
+    """The cycle observables of Sec. 4 (parabolic fits of the extrema) recover
+    the period and amplitude of a sampled sinusoid whose period is not a
+    multiple of the sample spacing, to the O(h^2) accuracy of the fit."""
+    from paper_1205_6333_amd import observables as OB
+    T, A, h = 517.3, 4.2, 1.0
+    t = np.arange(0.0, 6000.0, h)
+    y = 6.0 + A * np.cos(2 * np.pi * t / T + 0.7)
+    tc, dur, ta, amp = OB.cycles(t, y)
+    assert len(dur) == 10 and len(amp) >= 10
+    np.testing.assert_allclose(dur, T, rtol=0, atol=1e-3)
+    np.testing.assert_allclose(amp, A, rtol=2e-5)
+    tmax, ymax, tmin, ymin = OB.parabolic_extrema(t, y)
+    np.testing.assert_allclose(np.diff(tmax), T, atol=1e-3)
+    np.testing.assert_allclose(np.diff(tmin), T, atol=1e-3)
+    np.testing.assert_allclose((tmin - tmax[0]) % T, T / 2, atol=1e-3)
+    np.testing.assert_allclose(ymax - ymin[:len(ymax)].mean(), 2 * A, rtol=2e-5)
