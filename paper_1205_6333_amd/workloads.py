@@ -46,7 +46,11 @@ def _sequential_reject(draw, n: int, min_dist: float, batch: int = 8192,
     must lie in [0, boxsize))."""
     acc = np.empty((n, 3))
     count = 0
+    idle = 0
     while count < n:
+        if idle > 100:  # jammed: no candidate accepted in 100 batches
+            raise RuntimeError("cannot place %d spheres at minimum distance %g (placed %d)"
+                               % (n, min_dist, count))
         cand = draw(batch)
         ok = np.ones(len(cand), dtype=bool)
         if count:
@@ -82,6 +86,7 @@ def _sequential_reject(draw, n: int, min_dist: float, batch: int = 8192,
         take = min(n - count, len(c2))
         acc[count:count + take] = c2[:take]
         count += take
+        idle = 0 if take else idle + 1
     return acc
 
 
