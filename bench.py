@@ -36,6 +36,9 @@ Other rows of the hot path are measured with --workload (one JSON line each):
             (and Kahan, FP64) accumulation of the hydrodynamic interactions
             and positions, dt = 0.01 and 0.001, all runs in one launch per
             chunk; cycle duration and amplitude by parabolic fits of x_1(t)
+  membench  the O(N^2) memory-access micro-benchmarks of App. A: naive,
+            small-tiling and tiling kernels x linear / strided / unordered
+            maps x float / float4, N = 4096 ... 65536, time per pair
   copy      a plain device copy of --copy-mib MiB (calibrates HBM counters)
 """
 from __future__ import annotations
@@ -391,6 +394,45 @@ def run_precision(args, sd, W, dev):
                                    "averaged over windows of 1e4 tau_s"}}
 
 
+def run_membench(args, sd, W, dev):
+    import torch
+    kinds = {0: "naive", 1: "smalltiling", 2: "tiling"}
+    maps = {0: "linear", 1: "strided", 2: "unordered"}
+    rows = []
+    for n in (4096, 16384, 65536):
+        reps = 100 if n <= 16384 else 20
+        for width in (1, 4):
+            x = torch.randint(0, 7, (n,) if width == 1 else (n, 4), device=dev).float()
+            out = torch.empty_like(x)
+            for kind in kinds:
+                for m in maps:
+                    sd.sd_membench(kind, m, x, out)
+                    ev0 = torch.cuda.Event(enable_timing=True)
+                    ev1 = torch.cuda.Event(enable_timing=True)
+                    ev0.record()
+                    for _ in range(reps):
+                        sd.sd_membench(kind, m, x, out)
+                    ev1.record()
+                    torch.cuda.synchronize()
+                    t = ev0.elapsed_time(ev1) / 1e3 / reps
+                    rows.append({"n": n, "type": "float" if width == 1 else "float4",
+                                 "kernel": kinds[kind], "map": maps[m], "ms": t * 1e3,
+                                 "ps_per_pair": t / (float(n) * n) * 1e12,
+                                 "gb_per_s": float(n) * n * 4 * width / t / 1e9})
+        print("bench membench: n=%d done" % n, file=sys.stderr, flush=True)
+    big = [r for r in rows if r["n"] == 65536]
+    best = min(big, key=lambda r: r["ps_per_pair"] / (4 if r["type"] == "float4" else 1))
+    return {"metric": "ps per pair of the App. A memory-access micro-benchmarks at N=65536",
+            "value": best["ps_per_pair"], "unit": "ps/pair", "n_gpus": 1,
+            "higher_is_better": False, "dtype": "f32", "data": "synthetic", "rows": rows,
+            "best": best,
+            "config": {"workload": "App. A: N threads in work-groups of 128 each read N "
+                                   "elements (float or float4) through linear k, strided "
+                                   "131k mod N or unordered (131k + 64j) mod N maps; naive, "
+                                   "small tiling (one wave fills a 64-element LDS tile), "
+                                   "tiling (128-element tile); 100 repetitions (20 at N=65536)"}}
+
+
 def run_copy(args, dev):
     import torch
     m = int(args.copy_mib * 2 ** 20 // 4)
@@ -416,7 +458,7 @@ def main():
     ap.add_argument("--tune", action="store_true", help="autotune the kernel shape first (untimed)")
     ap.add_argument("--workload", default="product",
                     choices=["product", "timeloop", "batched", "adjoint", "lubrication", "fcc",
-                             "precision", "copy"])
+                             "precision", "membench", "copy"])
     ap.add_argument("--study-time", type=float, default=2.0e4,
                     help="simulated tau_s of --workload precision (the paper: 5e5)")
     ap.add_argument("--loop-steps", type=int, default=1000, help="steps of --workload timeloop")
@@ -440,6 +482,7 @@ def main():
               "lubrication": lambda: run_lubrication(args, sd, W, dev),
               "fcc": lambda: run_fcc(args, sd, W, dev),
               "precision": lambda: run_precision(args, sd, W, dev),
+              "membench": lambda: run_membench(args, sd, W, dev),
               "copy": lambda: run_copy(args, dev)}[args.workload]
         print(json.dumps(fn()))
         return 0

@@ -308,6 +308,40 @@ typedef struct sd_cluster_spec {
 sd_status sd_cluster_run(const sd_params* p, int64_t n, int32_t runs, const sd_cluster_spec* specs,
                          double* state, const double* force, double* traj, void* stream);
 
+/* ----------------------------------------------- memory-access benchmarks */
+
+/* The O(N^2) memory-access micro-benchmarks of App. A (not on the product's
+ * path; they characterise the j-data paths the product kernel chooses from). */
+typedef enum sd_mb_kernel {
+    SD_MB_NAIVE = 0,        /* every thread reads its N elements from global memory */
+    SD_MB_SMALLTILING = 1,  /* the first wave (64 threads) fills an LDS tile of 64
+                               elements; the work-group of 128 threads reads it */
+    SD_MB_TILING = 2        /* the whole work-group fills a tile of 128 elements */
+} sd_mb_kernel;
+
+typedef enum sd_mb_map {
+    SD_MB_LINEAR = 0,       /* access k reads element k */
+    SD_MB_STRIDED = 1,      /* element k p mod N, p = 131 */
+    SD_MB_UNORDERED = 2     /* element (k p + j M) mod N, M = 64, j the global id of
+                               the reading thread (naive) or of the thread that
+                               loads the tile slot (tiled kernels) */
+} sd_mb_map;
+
+typedef enum sd_mb_elem { SD_MB_FLOAT = 0, SD_MB_FLOAT4 = 1 } sd_mb_elem;
+
+#define SD_MB_MAX_N (1 << 22)
+
+/*
+ * sd_membench -- one launch of N threads in work-groups of 128:
+ *   out[j] = in[j] + sum over the N accesses of in[map(k)]
+ * (elementwise for float4).  The tiled kernels visit element m + k of the
+ * array through the map of the thread that loads tile slot k, for tiles
+ * m = 0, TILE, 2 TILE, ... (the last tile is cut at N).
+ *   in, out  device float[n] or float4[n] (16-byte aligned), n <= SD_MB_MAX_N.
+ */
+sd_status sd_membench(int32_t kind, int32_t map, int32_t elem, int64_t n, const void* in,
+                      void* out, void* stream);
+
 /* ------------------------------------------------------------------- tuning */
 
 /* Kernel shape of the all-pairs product. */

@@ -16,3 +16,5 @@ from .binding import lub, lubrication_forces, sd_mean_vector, sd_pack, sd_run_lu
 from . import autograd  # noqa: E402,F401
 from .binding import (SD_ACC_DS, SD_ACC_FP32, SD_ACC_FP64, SD_ACC_KAHAN, SD_POS_DS,  # noqa: E402,F401
                       SD_POS_FP32, SD_POS_FP64, cluster_frames, sd_cluster_run)
+from .binding import (SD_MB_LINEAR, SD_MB_NAIVE, SD_MB_SMALLTILING, SD_MB_STRIDED,  # noqa: E402,F401
+                      SD_MB_TILING, SD_MB_UNORDERED, sd_membench)

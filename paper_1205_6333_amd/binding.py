@@ -26,6 +26,9 @@ SD_BATCH_MAX_CLUSTER = 1024
 SD_ACC_FP32, SD_ACC_KAHAN, SD_ACC_DS, SD_ACC_FP64 = 0, 1, 2, 3
 SD_POS_FP32, SD_POS_DS, SD_POS_FP64 = 0, 1, 2
 SD_CLUSTER_MAX_N, SD_CLUSTER_MAX_RUNS = 64, 4096
+SD_MB_NAIVE, SD_MB_SMALLTILING, SD_MB_TILING = 0, 1, 2
+SD_MB_LINEAR, SD_MB_STRIDED, SD_MB_UNORDERED = 0, 1, 2
+SD_MB_FLOAT, SD_MB_FLOAT4 = 0, 1
 
 
 class SdParams(ctypes.Structure):
@@ -97,6 +100,7 @@ def lib() -> ctypes.CDLL:
             "sd_run_lub": [P, ctypes.POINTER(SdLub), i64, dp, dp, dp, d, i64, i64, i32, i32, vp],
             "sd_mean_vector": [i64, dp, dp, vp],
             "sd_cluster_run": [P, i64, i32, ctypes.POINTER(SdClusterSpec), dp, dp, dp, vp],
+            "sd_membench": [i32, i32, i32, i64, vp, vp, vp],
             "sd_profile_enable": [i32],
             "sd_profile_read": [ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double)],
             "sd_profile_reset": [],
@@ -394,6 +398,23 @@ def sd_cluster_run(state, force, specs, traj=None, *, params: SdParams = None, s
     check(lib().sd_cluster_run(ctypes.byref(p), n, runs, arr, _ptr(state), _ptr(force),
                                _ptr(traj), _stream(stream)))
     return traj if frames else None
+
+
+def sd_membench(kind: int, access: int, inp, out=None, stream=None):
+    """One App. A micro-benchmark launch.  inp: contiguous CUDA float32 tensor
+    of shape (n,) (float) or (n, 4) (float4).  Returns out (same shape)."""
+    import torch
+    if not (inp.is_cuda and inp.dtype == torch.float32 and inp.is_contiguous()
+            and (inp.dim() == 1 or (inp.dim() == 2 and inp.shape[1] == 4))):
+        raise ValueError("inp must be a contiguous float32 CUDA tensor of shape (n,) or (n, 4)")
+    elem = SD_MB_FLOAT if inp.dim() == 1 else SD_MB_FLOAT4
+    if out is None:
+        out = torch.empty_like(inp)
+    elif out.shape != inp.shape or out.dtype != inp.dtype or not out.is_contiguous():
+        raise ValueError("out must match inp")
+    check(lib().sd_membench(int(kind), int(access), elem, inp.shape[0], _ptr(inp), _ptr(out),
+                            _stream(stream)))
+    return out
 
 
 def sd_pack(v, precision: int = SD_FP32_KAHAN, out=None, stream=None):

@@ -166,3 +166,16 @@ def test_cluster_run_validation(L):
     assert call([good], params=b.params(box=30.0)) == b.SD_EUNSUPPORTED
     assert b.cluster_frames([dict(acc=0, pos=0, dt=0.1, steps=10, stride=3),
                              dict(acc=0, pos=0, dt=0.1, steps=10, stride=0)]) == 3
+
+
+def test_membench_validation(L):
+    from paper_1205_6333_amd import binding as b
+    vp = ctypes.c_void_p
+    ok = vp(1 << 20)
+    assert L.sd_membench(3, 0, 0, 10, ok, ok, None) == b.SD_EINVAL
+    assert L.sd_membench(0, 3, 0, 10, ok, ok, None) == b.SD_EINVAL
+    assert L.sd_membench(0, 0, 2, 10, ok, ok, None) == b.SD_EINVAL
+    assert L.sd_membench(0, 0, 0, 0, ok, ok, None) == b.SD_EINVAL
+    assert L.sd_membench(0, 0, 0, (1 << 22) + 1, ok, ok, None) == b.SD_EINVAL
+    assert L.sd_membench(0, 0, 1, 10, vp((1 << 20) + 4), ok, None) == b.SD_EALIGN
+    assert L.sd_membench(0, 0, 0, 10, None, ok, None) == b.SD_EINVAL
