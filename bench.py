@@ -249,6 +249,25 @@ def run_adjoint(args, sd, W, dev):
     return out
 
 
+def _pair_roofline(sd, n, fn):
+    """Run fn with the library's pair-kernel timing on; the roofline of the
+    pair kernel (35 flop per pair, HIP events on the launch stream)."""
+    import torch
+    torch.cuda.synchronize()
+    sd.sd_profile_reset()
+    sd.sd_profile_enable(True)
+    fn()
+    torch.cuda.synchronize()
+    sd.sd_profile_enable(False)
+    launches, ms = sd.sd_profile_read()
+    kern_ms = ms / max(1, launches)
+    achieved = FLOP_PER_PAIR * float(n) * n / (kern_ms * 1e-3) / 1e12
+    return {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+            "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None,
+            "frac_of_nonpacked_peak": achieved / PEAK_FP32_NONPACKED,
+            "kernel": "pair kernel", "pair_kernel_ms": kern_ms, "launches": launches}
+
+
 def run_lubrication(args, sd, W, dev):
     import torch
     n, steps = args.n, args.loop_steps
@@ -268,7 +287,9 @@ def run_lubrication(args, sd, W, dev):
     t_plain = _sync_time(lambda: sd.sd_run(x2, f4, 0.001, steps))
     fo = torch.empty_like(x)
     t_forces = _sync_time(lambda: [sd.lubrication_forces(x, vp, fd, fo) for _ in range(steps)])
+    roof = _pair_roofline(sd, n, lambda: sd.sd_run_lub(x, fd, vp, 0.001, 5))
     return {"metric": "Euler steps/s with lubrication at N=%d (FP32-comp pair kernel)" % n,
+            "roofline": roof,
             "value": steps / t_lub, "unit": "steps/s", "n_gpus": 1, "higher_is_better": True,
             "dtype": "f32", "data": "synthetic", "steps": steps,
             "ms_per_step": t_lub * 1e3 / steps, "ms_per_step_without_lubrication": t_plain * 1e3 / steps,
@@ -309,7 +330,9 @@ def run_fcc(args, sd, W, dev):
         x.copy_(torch.tensor(x0, device=dev))
         sd.sd_run(x, f4d, dt, 1, params=p, precision=sd.SD_FP64)
         t64 = _sync_time(lambda: sd.sd_run(x, f4d, dt, s64, params=p, precision=sd.SD_FP64))
+        roof = _pair_roofline(sd, n, lambda: sd.sd_run_lub(x, fd, vp, dt, 5, params=p))
         row = {"m": m, "n": n, "box": L, "ms_per_step": t_lub * 1e3 / steps,
+               "pair_kernel_ms": roof["pair_kernel_ms"], "pair_kernel_frac": roof["frac"],
                "ms_per_step_without_lubrication": t_plain * 1e3 / steps,
                "ms_per_step_fp64_without_lubrication": t64 * 1e3 / s64,
                "g_pairs_per_s": float(n) * n * steps / t_lub / 1e9,
@@ -322,6 +345,7 @@ def run_fcc(args, sd, W, dev):
             "value": big["ms_per_step"], "unit": "ms/step", "n_gpus": 1,
             "higher_is_better": False, "dtype": "f32", "data": "synthetic", "steps": steps,
             "ms_per_step": big["ms_per_step"], "table": rows,
+            "roofline": roof,
             "config": {"workload": "Sec. 3.3 benchmark: perfect fcc lattice, n=0.1/a^3, periodic "
                                    "cube with nearest-image interactions, F=(0,0,-1), RPY, "
                                    "lubrication s<1 with the previous velocities, Euler "
