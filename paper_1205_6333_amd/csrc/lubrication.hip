@@ -212,7 +212,7 @@ __global__ void __launch_bounds__(256)
 k_lub_force(const double* __restrict__ x, const double* __restrict__ v,
             const double* __restrict__ f_ext, int n, const CellGrid* __restrict__ g,
             const int* __restrict__ start, const int* __restrict__ order, LubConst lc,
-            double* __restrict__ f_out)
+            double* __restrict__ f_out, float4* __restrict__ rec32, double4* __restrict__ rec64)
 {
     const int i = blockIdx.x * 256 + threadIdx.x;
     if (i >= n) return;
@@ -259,8 +259,13 @@ k_lub_force(const double* __restrict__ x, const double* __restrict__ v,
             }
         }
     }
-    for (int k = 0; k < 3; ++k)
-        f_out[3 * (size_t)i + k] = (f_ext ? f_ext[3 * (size_t)i + k] : 0.0) + acc[k];
+    double fo[3];
+    for (int k = 0; k < 3; ++k) fo[k] = (f_ext ? f_ext[3 * (size_t)i + k] : 0.0) + acc[k];
+    // the FP64 vector and/or the force record the pair kernel reads
+    if (f_out)
+        for (int k = 0; k < 3; ++k) f_out[3 * (size_t)i + k] = fo[k];
+    if (rec32) rec32[i] = make_float4((float)fo[0], (float)fo[1], (float)fo[2], 0.0f);
+    if (rec64) rec64[i] = make_double4(fo[0], fo[1], fo[2], 0.0);
 }
 
 // Library workspace of the cell list: grid | cid[n] | count[MAX] | start[MAX+1] | order[n]
@@ -269,8 +274,11 @@ static size_t lub_ws_bytes(int64_t n)
     return 256 + 4 * (size_t)n * 2 + 4 * ((size_t)LUB_MAX_CELLS * 2 + 1) + 256;
 }
 
+// f_out (f64[3n]), rec32 (f32x4[n]) and rec64 (f64x4[n]) receive the forces
+// when non-null.
 sd_status lub_forces_impl(const sd_params* p, const sd_lub* lub, int64_t n, const double* x,
-                          const double* v, const double* f_ext, double* f_out, hipStream_t hs)
+                          const double* v, const double* f_ext, double* f_out, float4* rec32,
+                          double4* rec64, hipStream_t hs)
 {
     sd_status st;
     void* buf = nullptr;
@@ -304,7 +312,7 @@ sd_status lub_forces_impl(const sd_params* p, const sd_lub* lub, int64_t n, cons
     lc.rcut2 = rc * rc;
     lc.pc = pair_const(p);
     hipLaunchKernelGGL(k_lub_force, gp, dim3(256), 0, hs, x, v, f_ext, nn, g, start, order, lc,
-                       f_out);
+                       f_out, rec32, rec64);
     if ((e = hipGetLastError()) != hipSuccess)
         return fail(SD_EDEVICE, "lubrication launch: %s", hipGetErrorString(e));
     return SD_OK;
@@ -335,7 +343,7 @@ sd_status lubrication_forces(const sd_params* p, const sd_lub* lub, int64_t n, c
         (st = check_ptr(f_out, 8, "f_out")))
         return st;
     if (f_ext && (uintptr_t)f_ext % 8) return fail(SD_EALIGN, "f_ext is not 8-byte aligned");
-    return lub_forces_impl(p, lub, n, x, v, f_ext, f_out, (hipStream_t)stream);
+    return lub_forces_impl(p, lub, n, x, v, f_ext, f_out, nullptr, nullptr, (hipStream_t)stream);
 }
 
 sd_status sd_run_lub(const sd_params* p, const sd_lub* lub, int64_t n, double* x,
@@ -357,34 +365,36 @@ sd_status sd_run_lub(const sd_params* p, const sd_lub* lub, int64_t n, double* x
     const bool f64 = precision == SD_FP64;
     const size_t rec = f64 ? 32 : 16;
     const PairLaunch L = plan_pair(precision, n);
-    void *partial = nullptr, *stage = nullptr, *fbuf = nullptr;
+    void *partial = nullptr, *stage = nullptr, *F4 = nullptr;
     if ((st = ws_get(WS_PARTIAL, partial_bytes(L, n), &partial)) ||
         (st = ws_get(WS_STAGE, rec * (size_t)n, &stage)) ||
-        (st = ws_get(WS_LUB_F, (rec + 24) * (size_t)n, &fbuf)))
+        (st = ws_get(WS_LUB_F, rec * (size_t)n, &F4)))
         return st;
-    double* F = (double*)fbuf;                       // f64[3n] forces of the step
-    void* F4 = (char*)fbuf + 24 * (size_t)n;          // packed records
     const double mu0 = 1.0 / (6.0 * M_PI * p->eta * p->a);
+    // per step: forces with the correction (written straight into the force
+    // records of the pair kernel), pair kernel, then merge + integrate, which
+    // also stages the new positions for the next step
+    hipError_t e = f64 ? launch_stage_f64(x, (double4*)stage, (int)n, hs)
+                       : launch_stage_f32(x, (float4*)stage, (int)n, box_side(p), hs);
+    if (e != hipSuccess) return fail(SD_EDEVICE, "staging launch: %s", hipGetErrorString(e));
     for (int64_t s = 0; s < steps; ++s) {
         const int64_t k = step0 + s;
-        if ((st = lub_forces_impl(p, lub, n, x, v_prev, f_ext, F, hs))) return st;
-        hipError_t e = f64 ? launch_pack_f64(F, (double4*)F4, (int)n, hs)
-                           : launch_pack_f32(F, (float4*)F4, (int)n, hs);
-        if (e == hipSuccess)
-            e = f64 ? launch_stage_f64(x, (double4*)stage, (int)n, hs)
-                    : launch_stage_f32(x, (float4*)stage, (int)n, box_side(p), hs);
-        if (e != hipSuccess) return fail(SD_EDEVICE, "staging launch: %s", hipGetErrorString(e));
+        if ((st = lub_forces_impl(p, lub, n, x, v_prev, f_ext, nullptr,
+                                  f64 ? nullptr : (float4*)F4, f64 ? (double4*)F4 : nullptr, hs)))
+            return st;
         if ((st = run_pair(p, n, stage, F4, f64 ? nullptr : x, precision, (double*)partial, L, hs)))
             return st;
         // Euler: x += dt v, v_prev = v;  AB2: x += dt (3/2 v - 1/2 v_prev), v_prev = v
         const int mode = (integrator == SD_EULER) ? 0 : (k == 0 ? 1 : 2);
+        const bool next = s + 1 < steps;
         e = f64 ? launch_merge_integrate_f64((double*)partial, L.splits, (int)n, (const double4*)F4,
                                              mu0, x, mode ? v_prev : nullptr,
-                                             mode ? nullptr : v_prev, dt, mode, nullptr, hs)
+                                             mode ? nullptr : v_prev, dt, mode,
+                                             next ? (double4*)stage : nullptr, hs)
                 : launch_merge_integrate_f32((double*)partial, L.splits, (int)n, (const float4*)F4,
                                              mu0, x, mode ? v_prev : nullptr,
-                                             mode ? nullptr : v_prev, dt, mode, nullptr,
-                                             box_side(p), hs);
+                                             mode ? nullptr : v_prev, dt, mode,
+                                             next ? (float4*)stage : nullptr, box_side(p), hs);
         if (e != hipSuccess) return fail(SD_EDEVICE, "integrate launch: %s", hipGetErrorString(e));
     }
     return SD_OK;
