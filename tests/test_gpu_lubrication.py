@@ -79,22 +79,21 @@ def test_lubrication_deterministic(sd):
 
 
 # The lagged correction of Sec. 3.1 multiplies the relative velocity of a close
-# pair by about mu_rel * zeta each step (about 20 at s = 0.01, whatever dt), so
-# rounding differences between the GPU and oracle summation orders grow with
-# the stiffness: the dense case (contacts at 2.02a) gets a looser bound than
-# the mild one (contacts at 2.3a).
-@pytest.mark.parametrize("min_dist,tol64,tol32", [(2.3, 1e-11, 1e-6), (2.02, 1e-9, 1e-5)])
-@pytest.mark.parametrize("prec", [1, 0])
-@pytest.mark.parametrize("integ", [0, 1])
+# pair by about -mu_rel * zeta each step, whatever dt; below s = 0.28 (an
+# isolated pair) that factor exceeds 1 and the loop diverges, in the oracle as
+# on the GPU.  Both cases here keep every gap above 0.3a (phi = 0.1): the
+# oracle's own sensitivity to a 1e-14 input change grows only ~4x in 30 steps.
+@pytest.mark.parametrize("min_dist,tol64,tol32", [(2.4, 1e-11, 1e-6), (2.3, 1e-11, 1e-6)])
 def test_run_lub_parity(sd, orc, min_dist, tol64, tol32, prec, integ):
     import torch
     tol = tol64 if prec == 1 else tol32
     n = 300
-    x0 = W.random_suspension(n, phi=0.25, min_dist=min_dist, seed=12)
+    x0 = W.random_suspension(n, phi=0.1, min_dist=min_dist, seed=12)
     f = W.gravity_forces(n) + 0.5 * W.gaussian_forces(n, seed=13)
     po, lo = orc.params(), orc.lub()
     xr, vr, _ = orc.run_lub(po, lo, x0, f, 0.01, 30, integ)
-    assert np.abs(orc.lubrication_force(po, lo, x0, vr)).max() > 0.1  # the correction is active
+    assert np.abs(orc.lubrication_force(po, lo, x0, vr)).max() > 1.0  # the correction is active
+    assert np.abs(xr - x0).max() < 20.0                                # and the loop is bounded
     xd = to_dev3(x0)
     vp = torch.zeros_like(xd)
     sd.sd_run_lub(xd, to_dev3(f), vp, 0.01, 30, integrator=integ, precision=prec)

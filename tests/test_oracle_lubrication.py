@@ -126,3 +126,25 @@ def test_lubrication_is_a_hard_core(orc):
     assert np.linalg.norm(x_plain[0] - x_plain[1]) < 2.0
     gaps = np.linalg.norm(traj[:, 0] - traj[:, 1], axis=1)
     assert gaps.min() > 2.0
+
+
+@pytest.mark.parametrize("s_gap", [0.05, 0.2, 0.3, 0.6])
+def test_lagged_correction_multiplies_relative_velocity(orc, s_gap):
+    """Step 2 of Sec. 3.1 with the previous velocities: two spheres without
+    external force whose previous velocities are +-u along their line of
+    centres move next with relative velocity -mu_rel zeta_P times the previous
+    one, where mu_rel = 2 mu0 (1 - 3a/2r + a^3/r^3) (RPY, Eq. 7b, along the
+    line) and mu0 zeta_P = 1/(4s) - 9/40 log s (Eq. 8).  The factor exceeds 1
+    below s = 0.28: the explicit lagged loop is only stable for wider gaps."""
+    a = 1.0
+    r = (2.0 + s_gap) * a
+    p = orc.params()
+    x0 = np.array([[0.0, 0.0, 0.0], [r, 0.0, 0.0]])
+    u = 1e-3
+    vp = np.array([[u, 0.0, 0.0], [-u, 0.0, 0.0]])
+    _, v, _ = orc.run_lub(p, orc.lub(), x0, np.zeros((2, 3)), 1e-12, 1, v_prev=vp)
+    mu_rel = 2.0 * (1.0 - 3.0 * a / (2.0 * r) + a ** 3 / r ** 3)
+    zeta = 1.0 / (4.0 * s_gap) - 9.0 / 40.0 * np.log(s_gap)
+    ratio = (v[0, 0] - v[1, 0]) / (2 * u)
+    np.testing.assert_allclose(ratio, -mu_rel * zeta, rtol=1e-12)
+    assert (abs(ratio) > 1.0) == (s_gap < 0.28)
