@@ -84,6 +84,8 @@ def test_lubrication_deterministic(sd):
 # on the GPU.  Both cases here keep every gap above 0.3a (phi = 0.1): the
 # oracle's own sensitivity to a 1e-14 input change grows only ~4x in 30 steps.
 @pytest.mark.parametrize("min_dist,tol64,tol32", [(2.4, 1e-11, 1e-6), (2.3, 1e-11, 1e-6)])
+@pytest.mark.parametrize("prec", [1, 0])
+@pytest.mark.parametrize("integ", [0, 1])
 def test_run_lub_parity(sd, orc, min_dist, tol64, tol32, prec, integ):
     import torch
     tol = tol64 if prec == 1 else tol32
