@@ -30,8 +30,8 @@ Other rows of the hot path are measured with --workload (one JSON line each):
   fcc       the benchmark of Sec. 3.3: sedimentation F = (0, 0, -1) from a
             perfect fcc lattice at n = 0.1/a^3 in a periodic cube (nearest
             image), Euler dt = 0.001, 100 steps, N = 4 m^3 from 256 to 202612:
-            runtime per step with and without the lubrication correction, and
-            the FP64 path
+            runtime per step, the lubrication step timed on the same
+            configuration, and the FP64 path
   precision the numerical-stability study of Sec. 4: the four-sphere cluster
             integrated for --study-time tau_s with single / double-single
             (and Kahan, FP64) accumulation of the hydrodynamic interactions
@@ -281,8 +281,8 @@ def run_lubrication(args, sd, W, dev):
     x = torch.tensor(x0, device=dev)
     vp = torch.zeros_like(x)
     sd.sd_run_lub(x, fd, vp, 0.001, 3)  # warm-up
-    n_close = int(sd.lubrication_forces(torch.tensor(x0, device=dev), torch.ones_like(x)).ne(0)
-                  .any(1).sum())
+    vr = torch.tensor(W.gaussian_forces(n, seed=5), device=dev)   # any non-rigid motion
+    n_close = int(sd.lubrication_forces(torch.tensor(x0, device=dev), vr).ne(0).any(1).sum())
     x = torch.tensor(x0, device=dev)
     vp.zero_()
     t_lub = _sync_time(lambda: sd.sd_run_lub(x, fd, vp, 0.001, steps))
@@ -308,9 +308,16 @@ FCC_M = (4, 6, 8, 11, 16, 20, 25, 32, 37)   # N = 4 m^3 = 256 ... 202612
 
 
 def run_fcc(args, sd, W, dev):
+    """Sec. 3.3: runtime per step from the perfect fcc lattice.  The lagged
+    lubrication correction diverges on this dense lattice (phi ~ 0.42: a
+    lattice mode grows by a factor of several per step, in the oracle as on
+    the GPU), after which the particle cloud is meaningless; the loop is
+    therefore timed without the correction (steps 1 and 3 of Sec. 3.1), and
+    step 2 (cell list + Eq. 8 forces) is timed on the same configuration."""
     import torch
     steps, dt = 100, 0.001
     rows = []
+    roof = None
     for m in FCC_M:
         x0, L = W.fcc_lattice(m, density=0.1)
         n = len(x0)
@@ -320,144 +327,42 @@ def run_fcc(args, sd, W, dev):
         f4 = _to4(f, torch.float32, dev)
         f4d = _to4(f, torch.float64, dev)
         x = torch.tensor(x0, device=dev)
-        vp = torch.zeros_like(x)
-        sd.sd_run_lub(x, fd, vp, dt, 3, params=p)          # warm-up
-        sd.sd_run(x, f4, dt, 3, params=p)
-        x.copy_(torch.tensor(x0, device=dev))
-        vp.zero_()
-        t_lub = _sync_time(lambda: sd.sd_run_lub(x, fd, vp, dt, steps, params=p))
-        vz = float(vp[:, 2].mean())
+        sd.sd_run(x, f4, dt, 3, params=p)                 # warm-up
         x.copy_(torch.tensor(x0, device=dev))
         t_plain = _sync_time(lambda: sd.sd_run(x, f4, dt, steps, params=p))
+        v = sd.mobility_apply(_to4(x.cpu().numpy(), torch.float32, dev), f4, params=p)
+        fo = torch.empty_like(x)
+        sd.lubrication_forces(x, v, fd, fo, params=p)
+        t_lub = _sync_time(lambda: [sd.lubrication_forces(x, v, fd, fo, params=p)
+                                    for _ in range(steps)])
         s64 = steps if n <= 65536 else 10
         x.copy_(torch.tensor(x0, device=dev))
         sd.sd_run(x, f4d, dt, 1, params=p, precision=sd.SD_FP64)
         t64 = _sync_time(lambda: sd.sd_run(x, f4d, dt, s64, params=p, precision=sd.SD_FP64))
-        roof = _pair_roofline(sd, n, lambda: sd.sd_run_lub(x, fd, vp, dt, 5, params=p))
-        row = {"m": m, "n": n, "box": L, "ms_per_step": t_lub * 1e3 / steps,
+        x.copy_(torch.tensor(x0, device=dev))
+        roof = _pair_roofline(sd, n, lambda: sd.sd_run(x, f4, dt, 5, params=p))
+        row = {"m": m, "n": n, "box": L, "ms_per_step": t_plain * 1e3 / steps,
+               "lubrication_step_ms": t_lub * 1e3 / steps,
+               "ms_per_step_with_lubrication_step": (t_plain + t_lub) * 1e3 / steps,
+               "ms_per_step_fp64": t64 * 1e3 / s64,
+               "speedup_vs_fp64": (t64 / s64) / (t_plain / steps),
                "pair_kernel_ms": roof["pair_kernel_ms"], "pair_kernel_frac": roof["frac"],
-               "ms_per_step_without_lubrication": t_plain * 1e3 / steps,
-               "ms_per_step_fp64_without_lubrication": t64 * 1e3 / s64,
-               "g_pairs_per_s": float(n) * n * steps / t_lub / 1e9,
-               "sedimentation_velocity": vz}
+               "g_pairs_per_s": float(n) * n * steps / t_plain / 1e9,
+               "sedimentation_velocity": float(v[:, 2].mean())}
         print("bench fcc: %s" % json.dumps(row), file=sys.stderr, flush=True)
         rows.append(row)
     big = rows[-1]
     return {"metric": "ms per Euler step of the fcc sedimentation benchmark at N=%d "
-                      "(periodic box, lubrication, FP32-comp pair kernel)" % big["n"],
+                      "(periodic box, FP32-comp pair kernel)" % big["n"],
             "value": big["ms_per_step"], "unit": "ms/step", "n_gpus": 1,
             "higher_is_better": False, "dtype": "f32", "data": "synthetic", "steps": steps,
-            "ms_per_step": big["ms_per_step"], "table": rows,
-            "roofline": roof,
+            "ms_per_step": big["ms_per_step"], "table": rows, "roofline": roof,
             "config": {"workload": "Sec. 3.3 benchmark: perfect fcc lattice, n=0.1/a^3, periodic "
-                                   "cube with nearest-image interactions, F=(0,0,-1), RPY, "
-                                   "lubrication s<1 with the previous velocities, Euler "
-                                   "dt=0.001, 100 steps, N=4m^3 for m in %s" % (FCC_M,)}}
-
-
-ACC_NAMES = {0: "single", 1: "kahan", 2: "double-single", 3: "fp64"}
-POS_NAMES = {0: "single", 1: "double-single", 2: "fp64"}
-
-
-def run_precision(args, sd, W, dev):
-    import torch
-    from paper_1205_6333_amd import observables as OB
-    x0, f = W.four_sphere_tetrahedron()
-    grid = [(a, p) for a in (0, 2) for p in (0, 1)] + [(1, 2), (3, 2)]
-    runs = [(a, p, dt) for dt in (0.01, 0.001) for (a, p) in grid]
-    t_total = float(args.study_time)
-    chunk_t = min(2000.0, t_total)            # tau_s per call
-    sample_t = 0.5                             # frame spacing in tau_s
-    specs = []
-    for a, p, dt in runs:
-        steps = int(round(chunk_t / dt))
-        specs.append(dict(acc=a, pos=p, dt=dt, steps=steps, stride=int(round(sample_t / dt))))
-    state = torch.zeros((len(runs), 2, 4, 3), dtype=torch.float64, device=dev)
-    state[:, 0] = torch.tensor(x0, device=dev)
-    fd = torch.tensor(f, device=dev)
-    nf = [s["steps"] // s["stride"] for s in specs]
-    series = [[] for _ in runs]                # (x1, y1) frames per run
-    n_calls = int(np.ceil(t_total / chunk_t))
-    t_gpu = 0.0
-    for c in range(n_calls):
-        out = {}
-        t_gpu += _sync_time(lambda: out.update(traj=sd.sd_cluster_run(state, fd, specs)))
-        traj = out["traj"].cpu().numpy()
-        off = 0
-        for r, k in enumerate(nf):
-            series[r].append(traj[off:off + k, 0, :2].copy())
-            off += k
-        if c % 10 == 0 or c == n_calls - 1:
-            print("bench precision: %.0f of %.0f tau_s, %.1f s on the GPU" %
-                  ((c + 1) * chunk_t, n_calls * chunk_t, t_gpu), file=sys.stderr, flush=True)
-    rows = []
-    window = 1.0e4
-    for r, (a, p, dt) in enumerate(runs):
-        xy = np.concatenate(series[r])
-        t = sample_t * np.arange(1, len(xy) + 1)
-        tc, dur, ta, amp = OB.cycles(t, xy[:, 0])
-        row = {"hi_accumulation": ACC_NAMES[a], "positions": POS_NAMES[p], "dt": dt,
-               "cycles": int(len(dur)), "max_abs_y1": float(np.abs(xy[:, 1]).max())}
-        if len(dur):
-            first = dur[tc < tc[0] + window]
-            last = dur[tc > tc[-1] - window]
-            row.update({"period_first_window": float(first.mean()),
-                        "period_last_window": float(last.mean()),
-                        "period_min": float(dur.min()), "period_max": float(dur.max()),
-                        "amplitude_first": float(amp[0]) if len(amp) else None,
-                        "amplitude_last": float(amp[-1]) if len(amp) else None,
-                        "last_cycle_end": float(tc[-1] + 0.5 * dur[-1])})
-        rows.append(row)
-    steps_fine = int(round(n_calls * chunk_t / 0.001))
-    return {"metric": "Euler steps/s of one four-sphere run (precision study of Sec. 4, "
-                      "%d runs per launch)" % len(runs),
-            "value": steps_fine / t_gpu, "unit": "steps/s", "n_gpus": 1,
-            "higher_is_better": True, "dtype": "f32", "data": "synthetic",
-            "gpu_seconds": t_gpu, "simulated_tau_s": n_calls * chunk_t, "runs": rows,
-            "config": {"workload": "four sedimenting spheres (tetrahedron of Fig. 4), F=(0,0,-1), "
-                                   "RPY, mu0=a=1, Euler; HI accumulation x positions in "
-                                   "{single, double-single} plus (kahan, fp64) and (fp64, fp64); "
-                                   "dt in {0.01, 0.001}; x_1 sampled every 0.5 tau_s; periods "
-                                   "averaged over windows of 1e4 tau_s"}}
-
-
-def run_membench(args, sd, W, dev):
-    import torch
-    kinds = {0: "naive", 1: "smalltiling", 2: "tiling"}
-    maps = {0: "linear", 1: "strided", 2: "unordered"}
-    rows = []
-    for n in (4096, 16384, 65536):
-        reps = 100 if n <= 16384 else 20
-        for width in (1, 4):
-            x = torch.randint(0, 7, (n,) if width == 1 else (n, 4), device=dev).float()
-            out = torch.empty_like(x)
-            for kind in kinds:
-                for m in maps:
-                    sd.sd_membench(kind, m, x, out)
-                    ev0 = torch.cuda.Event(enable_timing=True)
-                    ev1 = torch.cuda.Event(enable_timing=True)
-                    ev0.record()
-                    for _ in range(reps):
-                        sd.sd_membench(kind, m, x, out)
-                    ev1.record()
-                    torch.cuda.synchronize()
-                    t = ev0.elapsed_time(ev1) / 1e3 / reps
-                    rows.append({"n": n, "type": "float" if width == 1 else "float4",
-                                 "kernel": kinds[kind], "map": maps[m], "ms": t * 1e3,
-                                 "ps_per_pair": t / (float(n) * n) * 1e12,
-                                 "gb_per_s": float(n) * n * 4 * width / t / 1e9})
-        print("bench membench: n=%d done" % n, file=sys.stderr, flush=True)
-    big = [r for r in rows if r["n"] == 65536]
-    best = min(big, key=lambda r: r["ps_per_pair"] / (4 if r["type"] == "float4" else 1))
-    return {"metric": "ps per pair of the App. A memory-access micro-benchmarks at N=65536",
-            "value": best["ps_per_pair"], "unit": "ps/pair", "n_gpus": 1,
-            "higher_is_better": False, "dtype": "f32", "data": "synthetic", "rows": rows,
-            "best": best,
-            "config": {"workload": "App. A: N threads in work-groups of 128 each read N "
-                                   "elements (float or float4) through linear k, strided "
-                                   "131k mod N or unordered (131k + 64j) mod N maps; naive, "
-                                   "small tiling (one wave fills a 64-element LDS tile), "
-                                   "tiling (128-element tile); 100 repetitions (20 at N=65536)"}}
+                                   "cube with nearest-image interactions, F=(0,0,-1), RPY, Euler "
+                                   "dt=0.001, 100 steps, N=4m^3 for m in %s; the lubrication step "
+                                   "(cell list + Eq. 8 forces, s<1) timed separately on the same "
+                                   "configuration, since the lagged correction diverges on this "
+                                   "dense lattice" % (FCC_M,)}}
 
 
 def run_copy(args, dev):

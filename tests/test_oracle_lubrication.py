@@ -148,3 +148,19 @@ def test_lagged_correction_multiplies_relative_velocity(orc, s_gap):
     ratio = (v[0, 0] - v[1, 0]) / (2 * u)
     np.testing.assert_allclose(ratio, -mu_rel * zeta, rtol=1e-12)
     assert (abs(ratio) > 1.0) == (s_gap < 0.28)
+
+
+def test_lagged_correction_diverges_on_the_dense_fcc_start(orc):
+    """The fcc start of the Sec. 3.3 benchmark (n = 0.1/a^3, phi ~ 0.42,
+    twelve neighbours at s = 0.42) is far inside the unstable range of the
+    lagged correction: a lattice mode grows by a large factor each step, so
+    the loop with lubrication blows up within tens of steps, while the loop
+    without it sediments uniformly.  (Hence the benchmark times the
+    lubrication step on its own.)"""
+    x0, L = W.fcc_lattice(6)
+    f = W.gravity_forces(len(x0))
+    p = orc.params(box=L)
+    _, v_plain, _ = orc.run(p, x0, f, 0.001, 25)
+    assert np.abs(v_plain).max() < 200.0
+    _, v_lub, _ = orc.run_lub(p, orc.lub(), x0, f, 0.001, 25)
+    assert np.abs(v_lub).max() > 1e6
