@@ -365,6 +365,111 @@ def run_fcc(args, sd, W, dev):
                                    "dense lattice" % (FCC_M,)}}
 
 
+ACC_NAMES = {0: "single", 1: "kahan", 2: "double-single", 3: "fp64"}
+POS_NAMES = {0: "single", 1: "double-single", 2: "fp64"}
+
+
+def run_precision(args, sd, W, dev):
+    import torch
+    from paper_1205_6333_amd import observables as OB
+    x0, f = W.four_sphere_tetrahedron()
+    grid = [(a, p) for a in (0, 2) for p in (0, 1)] + [(1, 2), (3, 2)]
+    runs = [(a, p, dt) for dt in (0.01, 0.001) for (a, p) in grid]
+    t_total = float(args.study_time)
+    chunk_t = min(2000.0, t_total)            # tau_s per call
+    sample_t = 0.5                             # frame spacing in tau_s
+    specs = []
+    for a, p, dt in runs:
+        steps = int(round(chunk_t / dt))
+        specs.append(dict(acc=a, pos=p, dt=dt, steps=steps, stride=int(round(sample_t / dt))))
+    state = torch.zeros((len(runs), 2, 4, 3), dtype=torch.float64, device=dev)
+    state[:, 0] = torch.tensor(x0, device=dev)
+    fd = torch.tensor(f, device=dev)
+    nf = [s["steps"] // s["stride"] for s in specs]
+    series = [[] for _ in runs]                # (x1, y1) frames per run
+    n_calls = int(np.ceil(t_total / chunk_t))
+    t_gpu = 0.0
+    for c in range(n_calls):
+        out = {}
+        t_gpu += _sync_time(lambda: out.update(traj=sd.sd_cluster_run(state, fd, specs)))
+        traj = out["traj"].cpu().numpy()
+        off = 0
+        for r, k in enumerate(nf):
+            series[r].append(traj[off:off + k, 0, :2].copy())
+            off += k
+        if c % 10 == 0 or c == n_calls - 1:
+            print("bench precision: %.0f of %.0f tau_s, %.1f s on the GPU" %
+                  ((c + 1) * chunk_t, n_calls * chunk_t, t_gpu), file=sys.stderr, flush=True)
+    rows = []
+    window = 1.0e4
+    for r, (a, p, dt) in enumerate(runs):
+        xy = np.concatenate(series[r])
+        t = sample_t * np.arange(1, len(xy) + 1)
+        tc, dur, ta, amp = OB.cycles(t, xy[:, 0])
+        row = {"hi_accumulation": ACC_NAMES[a], "positions": POS_NAMES[p], "dt": dt,
+               "cycles": int(len(dur)), "max_abs_y1": float(np.abs(xy[:, 1]).max())}
+        if len(dur):
+            first = dur[tc < tc[0] + window]
+            last = dur[tc > tc[-1] - window]
+            row.update({"period_first_window": float(first.mean()),
+                        "period_last_window": float(last.mean()),
+                        "period_min": float(dur.min()), "period_max": float(dur.max()),
+                        "amplitude_first": float(amp[0]) if len(amp) else None,
+                        "amplitude_last": float(amp[-1]) if len(amp) else None,
+                        "last_cycle_end": float(tc[-1] + 0.5 * dur[-1])})
+        rows.append(row)
+    steps_fine = int(round(n_calls * chunk_t / 0.001))
+    return {"metric": "Euler steps/s of one four-sphere run (precision study of Sec. 4, "
+                      "%d runs per launch)" % len(runs),
+            "value": steps_fine / t_gpu, "unit": "steps/s", "n_gpus": 1,
+            "higher_is_better": True, "dtype": "f32", "data": "synthetic",
+            "gpu_seconds": t_gpu, "simulated_tau_s": n_calls * chunk_t, "runs": rows,
+            "config": {"workload": "four sedimenting spheres (tetrahedron of Fig. 4), F=(0,0,-1), "
+                                   "RPY, mu0=a=1, Euler; HI accumulation x positions in "
+                                   "{single, double-single} plus (kahan, fp64) and (fp64, fp64); "
+                                   "dt in {0.01, 0.001}; x_1 sampled every 0.5 tau_s; periods "
+                                   "averaged over windows of 1e4 tau_s"}}
+
+
+def run_membench(args, sd, W, dev):
+    import torch
+    kinds = {0: "naive", 1: "smalltiling", 2: "tiling"}
+    maps = {0: "linear", 1: "strided", 2: "unordered"}
+    rows = []
+    for n in (4096, 16384, 65536):
+        reps = 100 if n <= 16384 else 20
+        for width in (1, 4):
+            x = torch.randint(0, 7, (n,) if width == 1 else (n, 4), device=dev).float()
+            out = torch.empty_like(x)
+            for kind in kinds:
+                for m in maps:
+                    sd.sd_membench(kind, m, x, out)
+                    ev0 = torch.cuda.Event(enable_timing=True)
+                    ev1 = torch.cuda.Event(enable_timing=True)
+                    ev0.record()
+                    for _ in range(reps):
+                        sd.sd_membench(kind, m, x, out)
+                    ev1.record()
+                    torch.cuda.synchronize()
+                    t = ev0.elapsed_time(ev1) / 1e3 / reps
+                    rows.append({"n": n, "type": "float" if width == 1 else "float4",
+                                 "kernel": kinds[kind], "map": maps[m], "ms": t * 1e3,
+                                 "ps_per_pair": t / (float(n) * n) * 1e12,
+                                 "gb_per_s": float(n) * n * 4 * width / t / 1e9})
+        print("bench membench: n=%d done" % n, file=sys.stderr, flush=True)
+    big = [r for r in rows if r["n"] == 65536]
+    best = min(big, key=lambda r: r["ps_per_pair"] / (4 if r["type"] == "float4" else 1))
+    return {"metric": "ps per pair of the App. A memory-access micro-benchmarks at N=65536",
+            "value": best["ps_per_pair"], "unit": "ps/pair", "n_gpus": 1,
+            "higher_is_better": False, "dtype": "f32", "data": "synthetic", "rows": rows,
+            "best": best,
+            "config": {"workload": "App. A: N threads in work-groups of 128 each read N "
+                                   "elements (float or float4) through linear k, strided "
+                                   "131k mod N or unordered (131k + 64j) mod N maps; naive, "
+                                   "small tiling (one wave fills a 64-element LDS tile), "
+                                   "tiling (128-element tile); 100 repetitions (20 at N=65536)"}}
+
+
 def run_copy(args, dev):
     import torch
     m = int(args.copy_mib * 2 ** 20 // 4)
