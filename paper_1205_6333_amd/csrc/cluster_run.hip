@@ -44,15 +44,16 @@ __device__ __forceinline__ void ds_add(float& hi, float& lo, float bh, float bl)
     lo = e - (hi - s);
 }
 
-template <int TENSOR>
-__global__ void __launch_bounds__(64)
-k_cluster_run(const ClusterRunDev* __restrict__ runs, int n, PairConst pc,
-              double* __restrict__ state, const double* __restrict__ force,
-              double* __restrict__ traj)
+// One run, its precisions fixed at compile time (ACC: sd_acc_mode, POS:
+// sd_pos_mode), so that the step loop carries no mode branches.
+template <int TENSOR, int ACC, int POS>
+__device__ __forceinline__ void cluster_body(const ClusterRunDev& R, int n, const PairConst& pc,
+                                             double* __restrict__ state,
+                                             const double* __restrict__ force,
+                                             double* __restrict__ traj, float (*s_hi)[64],
+                                             float (*s_lo)[64], double (*s_x)[64],
+                                             double (*s_f)[64])
 {
-    __shared__ float s_hi[3][64], s_lo[3][64];
-    __shared__ double s_x[3][64];
-    const ClusterRunDev R = runs[blockIdx.x];
     const int i = threadIdx.x;
     const bool act = i < n;
     double* st = state + (size_t)blockIdx.x * 6 * (size_t)n;
@@ -65,26 +66,28 @@ k_cluster_run(const ClusterRunDev* __restrict__ runs, int n, PairConst pc,
         const double v = act ? st[3 * i + k] + st[3 * (size_t)n + 3 * i + k] : 0.0;
         f[k] = act ? force[3 * i + k] : 0.0;
         xh[k] = (float)v;
-        xl[k] = (R.pos == SD_POS_FP32) ? 0.0f : (float)(v - (double)xh[k]);
-        x64[k] = (R.pos == SD_POS_FP64) ? v : (double)xh[k] + (double)xl[k];
+        xl[k] = (POS == SD_POS_FP32) ? 0.0f : (float)(v - (double)xh[k]);
+        x64[k] = (POS == SD_POS_FP64) ? v : (double)xh[k] + (double)xl[k];
     }
     const float gamma = pc.gamma_f, m3g = pc.m3gamma_f, thr2 = pc.thr2_f;
+    // the constant forces stay in LDS for the whole call
+    for (int k = 0; k < 3; ++k) s_f[k][i] = f[k];
 
     long long frame = R.frame0, since = 0;  // next frame, steps since the last one
     for (long long step = 0; step < R.steps; ++step) {
         for (int k = 0; k < 3; ++k) {
-            s_hi[k][i] = xh[k];
-            s_lo[k][i] = xl[k];
+            if (ACC != SD_ACC_FP64) s_hi[k][i] = xh[k];
+            if (ACC != SD_ACC_FP64 && POS != SD_POS_FP32) s_lo[k][i] = xl[k];
             s_x[k][i] = x64[k];
         }
         __syncthreads();
         double v[3];
-        if (R.acc == SD_ACC_FP64) {
+        if (ACC == SD_ACC_FP64) {
             double a0 = 0.0, a1 = 0.0, a2 = 0.0;
             for (int j = 0; j < n; ++j) {
                 if (j == i) continue;
                 near_term<TENSOR>(pc, x64[0] - s_x[0][j], x64[1] - s_x[1][j], x64[2] - s_x[2][j],
-                                  force[3 * j], force[3 * j + 1], force[3 * j + 2], a0, a1, a2);
+                                  s_f[0][j], s_f[1][j], s_f[2][j], a0, a1, a2);
             }
             v[0] = pc.mu0 * f[0] + a0;
             v[1] = pc.mu0 * f[1] + a1;
@@ -95,12 +98,14 @@ k_cluster_run(const ClusterRunDev* __restrict__ runs, int n, PairConst pc,
             double n0 = 0.0, n1 = 0.0, n2 = 0.0;    // FP64 near pairs (physical units)
             for (int j = 0; j < n; ++j) {
                 if (j == i) continue;
-                const float dx = (xh[0] - s_hi[0][j]) + (xl[0] - s_lo[0][j]);
-                const float dy = (xh[1] - s_hi[1][j]) + (xl[1] - s_lo[1][j]);
-                const float dz = (xh[2] - s_hi[2][j]) + (xl[2] - s_lo[2][j]);
+                float dx = xh[0] - s_hi[0][j], dy = xh[1] - s_hi[1][j], dz = xh[2] - s_hi[2][j];
+                if (POS != SD_POS_FP32) {
+                    dx += xl[0] - s_lo[0][j];
+                    dy += xl[1] - s_lo[1][j];
+                    dz += xl[2] - s_lo[2][j];
+                }
                 const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
-                const float fx = (float)force[3 * j], fy = (float)force[3 * j + 1],
-                            fz = (float)force[3 * j + 2];
+                const float fx = (float)s_f[0][j], fy = (float)s_f[1][j], fz = (float)s_f[2][j];
                 if (r2 < thr2) {
                     near_term<TENSOR>(pc, x64[0] - s_x[0][j], x64[1] - s_x[1][j],
                                       x64[2] - s_x[2][j], (double)fx, (double)fy, (double)fz, n0,
@@ -121,11 +126,11 @@ k_cluster_run(const ClusterRunDev* __restrict__ runs, int n, PairConst pc,
                 const float t0 = fmaf(A, fx, sB * dx);
                 const float t1 = fmaf(A, fy, sB * dy);
                 const float t2 = fmaf(A, fz, sB * dz);
-                if (R.acc == SD_ACC_FP32) {
+                if (ACC == SD_ACC_FP32) {
                     s0 += t0;
                     s1 += t1;
                     s2 += t2;
-                } else if (R.acc == SD_ACC_KAHAN) {
+                } else if (ACC == SD_ACC_KAHAN) {
                     const float y0 = t0 - c0, y1 = t1 - c1, y2 = t2 - c2;
                     const float u0 = s0 + y0, u1 = s1 + y1, u2 = s2 + y2;
                     c0 = (u0 - s0) - y0;
@@ -141,7 +146,7 @@ k_cluster_run(const ClusterRunDev* __restrict__ runs, int n, PairConst pc,
                 }
             }
             // Kahan: the sum is s - c; double-single: s + c
-            const double sg = (R.acc == SD_ACC_KAHAN) ? -1.0 : 1.0;
+            const double sg = (ACC == SD_ACC_KAHAN) ? -1.0 : 1.0;
             v[0] = pc.mu0 * f[0] + pc.alpha * ((double)s0 + sg * (double)c0) + n0;
             v[1] = pc.mu0 * f[1] + pc.alpha * ((double)s1 + sg * (double)c1) + n1;
             v[2] = pc.mu0 * f[2] + pc.alpha * ((double)s2 + sg * (double)c2) + n2;
@@ -149,10 +154,10 @@ k_cluster_run(const ClusterRunDev* __restrict__ runs, int n, PairConst pc,
         // Euler update in the run's position precision
         for (int k = 0; k < 3; ++k) {
             const double inc = R.dt * v[k];
-            if (R.pos == SD_POS_FP32) {
+            if (POS == SD_POS_FP32) {
                 xh[k] = xh[k] + (float)inc;
                 x64[k] = (double)xh[k];
-            } else if (R.pos == SD_POS_DS) {
+            } else if (POS == SD_POS_DS) {
                 const float ih = (float)inc;
                 ds_add(xh[k], xl[k], ih, (float)(inc - (double)ih));
                 x64[k] = (double)xh[k] + (double)xl[k];
@@ -176,14 +181,34 @@ k_cluster_run(const ClusterRunDev* __restrict__ runs, int n, PairConst pc,
     }
     if (act)
         for (int k = 0; k < 3; ++k) {
-            if (R.pos == SD_POS_DS) {
+            if (POS == SD_POS_DS) {
                 st[3 * i + k] = (double)xh[k];
                 st[3 * (size_t)n + 3 * i + k] = (double)xl[k];
             } else {
-                st[3 * i + k] = (R.pos == SD_POS_FP32) ? (double)xh[k] : x64[k];
+                st[3 * i + k] = (POS == SD_POS_FP32) ? (double)xh[k] : x64[k];
                 st[3 * (size_t)n + 3 * i + k] = 0.0;
             }
         }
+}
+
+
+template <int TENSOR>
+__global__ void __launch_bounds__(64)
+k_cluster_run(const ClusterRunDev* __restrict__ runs, int n, PairConst pc,
+              double* __restrict__ state, const double* __restrict__ force,
+              double* __restrict__ traj)
+{
+    __shared__ float s_hi[3][64], s_lo[3][64];
+    __shared__ double s_x[3][64], s_f[3][64];
+    const ClusterRunDev R = runs[blockIdx.x];
+#define SD_CR(A, P)                                                                            \
+    if (R.acc == A && R.pos == P) {                                                            \
+        cluster_body<TENSOR, A, P>(R, n, pc, state, force, traj, s_hi, s_lo, s_x, s_f);        \
+        return;                                                                                \
+    }
+    SD_CR(0, 0) SD_CR(0, 1) SD_CR(0, 2) SD_CR(1, 0) SD_CR(1, 1) SD_CR(1, 2)
+    SD_CR(2, 0) SD_CR(2, 1) SD_CR(2, 2) SD_CR(3, 0) SD_CR(3, 1) SD_CR(3, 2)
+#undef SD_CR
 }
 
 }  // namespace sd
