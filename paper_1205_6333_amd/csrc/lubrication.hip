@@ -15,12 +15,15 @@
 #include "sd_host.h"
 #include "sd_internal.h"
 
+#include <algorithm>
 #include <cmath>
 
 namespace sd {
 
 constexpr int LUB_MAX_CELLS = 1 << 21;   // cap of the cell grid (cells grow beyond the cutoff if needed)
-constexpr int SCAN_T = 1024;
+constexpr int SCAN_B = 2048;                          // cells per scan block (256 threads x 8)
+constexpr int SCAN_NB = LUB_MAX_CELLS / SCAN_B;       // 1024 scan blocks at most
+constexpr int BBOX_NB = 1024;                         // bounding-box partials at most
 
 struct CellGrid {
     double lo[3];
@@ -35,9 +38,46 @@ struct LubConst {
     PairConst pc;    // box for the nearest image
 };
 
-// bounding box -> cell grid (one work-group; fixed-order reduction)
-__global__ void __launch_bounds__(256) k_lub_grid(const double* __restrict__ x, int n, double hmin,
-                                                  double box, CellGrid* __restrict__ g)
+// Bounding box, stage 1: work-group b reduces particles [b chunk, (b+1) chunk)
+// to part[b] = (lo xyz, hi xyz).  min / max are exact, so the result does not
+// depend on the reduction order.
+__global__ void __launch_bounds__(256) k_lub_bbox(const double* __restrict__ x, int n, int chunk,
+                                                  double* __restrict__ part)
+{
+    __shared__ double lo[3][256], hi[3][256];
+    const int t = threadIdx.x;
+    const int b0 = blockIdx.x * chunk, b1 = min(n, b0 + chunk);
+    double l[3] = { 1e300, 1e300, 1e300 }, u[3] = { -1e300, -1e300, -1e300 };
+    for (int i = b0 + t; i < b1; i += 256)
+        for (int k = 0; k < 3; ++k) {
+            const double v = x[3 * (size_t)i + k];
+            l[k] = fmin(l[k], v);
+            u[k] = fmax(u[k], v);
+        }
+    for (int k = 0; k < 3; ++k) {
+        lo[k][t] = l[k];
+        hi[k][t] = u[k];
+    }
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (t < w)
+            for (int k = 0; k < 3; ++k) {
+                lo[k][t] = fmin(lo[k][t], lo[k][t + w]);
+                hi[k][t] = fmax(hi[k][t], hi[k][t + w]);
+            }
+        __syncthreads();
+    }
+    if (t < 3) {
+        part[6 * blockIdx.x + t] = lo[t][0];
+        part[6 * blockIdx.x + 3 + t] = hi[t][0];
+    }
+}
+
+// Bounding box, stage 2 (one work-group) -> cell grid; free space reduces the
+// nparts partials, a periodic box tiles the cube.
+__global__ void __launch_bounds__(256) k_lub_grid(const double* __restrict__ part, int nparts,
+                                                  double hmin, double box,
+                                                  CellGrid* __restrict__ g)
 {
     if (box > 0.0) {  // periodic: the grid tiles the box, cells no smaller than hmin
         if (threadIdx.x == 0) {
@@ -56,11 +96,10 @@ __global__ void __launch_bounds__(256) k_lub_grid(const double* __restrict__ x, 
     __shared__ double lo[3][256], hi[3][256];
     const int t = threadIdx.x;
     double l[3] = { 1e300, 1e300, 1e300 }, u[3] = { -1e300, -1e300, -1e300 };
-    for (int i = t; i < n; i += 256)
+    for (int b = t; b < nparts; b += 256)
         for (int k = 0; k < 3; ++k) {
-            const double v = x[3 * (size_t)i + k];
-            l[k] = fmin(l[k], v);
-            u[k] = fmax(u[k], v);
+            l[k] = fmin(l[k], part[6 * b + k]);
+            u[k] = fmax(u[k], part[6 * b + 3 + k]);
         }
     for (int k = 0; k < 3; ++k) {
         lo[k][t] = l[k];
@@ -146,36 +185,81 @@ __global__ void __launch_bounds__(256) k_lub_count(const double* __restrict__ x,
     atomicAdd(&count[c], 1);
 }
 
-// exclusive scan of the cell counts (one work-group), start[ncell] = n;
-// the counts are reset to zero for use as scatter cursors
-__global__ void __launch_bounds__(SCAN_T) k_lub_scan(int* __restrict__ count,
-                                                     int* __restrict__ start,
-                                                     const CellGrid* __restrict__ g, int n)
+// Exclusive scan of the cell counts in three passes: per-block sums of SCAN_B
+// cells, a scan of the (at most SCAN_NB) block sums in one work-group, then
+// each block scans its cells from its offset.  start[ncell] = n; the counts
+// are reset to zero for use as scatter cursors.  Integer sums: the result is
+// exact and independent of the order.
+__device__ __forceinline__ int block_exclusive_scan_256(int v, int* sh)
 {
-    __shared__ int part[SCAN_T];
     const int t = threadIdx.x;
-    const int nc = g->ncell;
-    const int chunk = (nc + SCAN_T - 1) / SCAN_T;
-    const int b = t * chunk, e = min(nc, b + chunk);
-    int sum = 0;
-    for (int c = b; c < e; ++c) sum += count[c];
-    part[t] = sum;
+    sh[t] = v;
     __syncthreads();
-    // Hillis-Steele inclusive scan of the per-thread sums
-    for (int w = 1; w < SCAN_T; w <<= 1) {
-        const int v = t >= w ? part[t - w] : 0;
+    for (int w = 1; w < 256; w <<= 1) {
+        const int a = t >= w ? sh[t - w] : 0;
         __syncthreads();
-        part[t] += v;
+        sh[t] += a;
         __syncthreads();
     }
-    int run = part[t] - sum;
-    for (int c = b; c < e; ++c) {
-        const int k = count[c];
-        start[c] = run;
-        run += k;
-        count[c] = 0;
+    const int incl = sh[t];
+    __syncthreads();
+    return incl - v;
+}
+
+__global__ void __launch_bounds__(256) k_lub_scan_sums(const int* __restrict__ count,
+                                                       const CellGrid* __restrict__ g,
+                                                       int* __restrict__ bsum)
+{
+    __shared__ int sh[256];
+    const int nc = g->ncell;
+    const int c0 = blockIdx.x * SCAN_B + threadIdx.x * (SCAN_B / 256);
+    if (blockIdx.x * SCAN_B >= nc) return;   // uniform per block
+    int v = 0;
+    for (int c = c0; c < c0 + SCAN_B / 256; ++c)
+        if (c < nc) v += count[c];
+    const int ex = block_exclusive_scan_256(v, sh);
+    if (threadIdx.x == 255) bsum[blockIdx.x] = ex + v;
+}
+
+__global__ void __launch_bounds__(1024) k_lub_scan_top(int* __restrict__ bsum,
+                                                       const CellGrid* __restrict__ g)
+{
+    __shared__ int sh[1024];
+    const int t = threadIdx.x;
+    const int nb = (g->ncell + SCAN_B - 1) / SCAN_B;
+    const int v = t < nb ? bsum[t] : 0;
+    sh[t] = v;
+    __syncthreads();
+    for (int w = 1; w < 1024; w <<= 1) {
+        const int a = t >= w ? sh[t - w] : 0;
+        __syncthreads();
+        sh[t] += a;
+        __syncthreads();
     }
-    if (t == 0) start[nc] = n;
+    if (t < nb) bsum[t] = sh[t] - v;   // exclusive offsets
+}
+
+__global__ void __launch_bounds__(256) k_lub_scan_apply(int* __restrict__ count,
+                                                        int* __restrict__ start,
+                                                        const int* __restrict__ boff,
+                                                        const CellGrid* __restrict__ g, int n)
+{
+    __shared__ int sh[256];
+    const int nc = g->ncell;
+    if (blockIdx.x * SCAN_B >= nc) return;   // uniform per block
+    const int c0 = blockIdx.x * SCAN_B + threadIdx.x * (SCAN_B / 256);
+    int v = 0;
+    for (int c = c0; c < c0 + SCAN_B / 256; ++c)
+        if (c < nc) v += count[c];
+    int run = boff[blockIdx.x] + block_exclusive_scan_256(v, sh);
+    for (int c = c0; c < c0 + SCAN_B / 256; ++c)
+        if (c < nc) {
+            const int k = count[c];
+            start[c] = run;
+            run += k;
+            count[c] = 0;
+        }
+    if (blockIdx.x == 0 && threadIdx.x == 0) start[nc] = n;
 }
 
 __global__ void __launch_bounds__(256) k_lub_scatter(const int* __restrict__ cid, int n,
@@ -268,10 +352,12 @@ k_lub_force(const double* __restrict__ x, const double* __restrict__ v,
     if (rec64) rec64[i] = make_double4(fo[0], fo[1], fo[2], 0.0);
 }
 
-// Library workspace of the cell list: grid | cid[n] | count[MAX] | start[MAX+1] | order[n]
+// Library workspace of the cell list: grid | bbox partials f64[6 BBOX_NB] |
+// block sums int[SCAN_NB] | cid[n] | order[n] | count[MAX] | start[MAX+1]
 static size_t lub_ws_bytes(int64_t n)
 {
-    return 256 + 4 * (size_t)n * 2 + 4 * ((size_t)LUB_MAX_CELLS * 2 + 1) + 256;
+    return 256 + 48 * (size_t)BBOX_NB + 4 * (size_t)SCAN_NB + 4 * (size_t)n * 2 +
+           4 * ((size_t)LUB_MAX_CELLS * 2 + 1) + 256;
 }
 
 // f_out (f64[3n]), rec32 (f32x4[n]) and rec64 (f64x4[n]) receive the forces
@@ -286,6 +372,10 @@ sd_status lub_forces_impl(const sd_params* p, const sd_lub* lub, int64_t n, cons
     char* q = (char*)buf;
     CellGrid* g = (CellGrid*)q;
     q += 256;
+    double* bbox = (double*)q;
+    q += 48 * (size_t)BBOX_NB;
+    int* bsum = (int*)q;
+    q += 4 * (size_t)SCAN_NB;
     int* cid = (int*)q;
     q += 4 * (size_t)n;
     int* order = (int*)q;
@@ -297,10 +387,19 @@ sd_status lub_forces_impl(const sd_params* p, const sd_lub* lub, int64_t n, cons
     const dim3 gp((unsigned)((n + 255) / 256));
     hipError_t e = launch_fill_i32(count, 0, LUB_MAX_CELLS, hs);
     if (e != hipSuccess) return fail(SD_EDEVICE, "fill launch: %s", hipGetErrorString(e));
-    hipLaunchKernelGGL(k_lub_grid, dim3(1), dim3(256), 0, hs, x, nn, (2.0 + lub->s_cut) * p->a,
-                       box_side(p), g);
+    int nparts = 0;
+    if (!(box_side(p) > 0.0)) {  // free space: bounding box of the particles
+        nparts = (int)std::min<int64_t>(BBOX_NB, std::max<int64_t>(1, (n + 4095) / 4096));
+        const int chunk = (int)((n + nparts - 1) / nparts);
+        hipLaunchKernelGGL(k_lub_bbox, dim3(nparts), dim3(256), 0, hs, x, nn, chunk, bbox);
+    }
+    hipLaunchKernelGGL(k_lub_grid, dim3(1), dim3(256), 0, hs, bbox, nparts,
+                       (2.0 + lub->s_cut) * p->a, box_side(p), g);
     hipLaunchKernelGGL(k_lub_count, gp, dim3(256), 0, hs, x, nn, g, cid, count);
-    hipLaunchKernelGGL(k_lub_scan, dim3(1), dim3(SCAN_T), 0, hs, count, start, g, nn);
+    hipLaunchKernelGGL(k_lub_scan_sums, dim3(SCAN_NB), dim3(256), 0, hs, count, g, bsum);
+    hipLaunchKernelGGL(k_lub_scan_top, dim3(1), dim3(1024), 0, hs, bsum, g);
+    hipLaunchKernelGGL(k_lub_scan_apply, dim3(SCAN_NB), dim3(256), 0, hs, count, start, bsum, g,
+                       nn);
     hipLaunchKernelGGL(k_lub_scatter, gp, dim3(256), 0, hs, cid, nn, start, count, order);
     hipLaunchKernelGGL(k_lub_sort, dim3(LUB_MAX_CELLS / 256), dim3(256), 0, hs, start, order, g);
     LubConst lc;
