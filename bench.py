@@ -62,10 +62,10 @@ METRIC = "G pair-interactions/s of RPY mobility product at N=65536 (FP32-comp vs
 # scaled by what the counter reads for a plain 256 MiB copy (fetch x 2.00,
 # write x 1.00).  Valid only for the kernel source (SHA-1 of mobility.hip) and
 # launch configuration the counters were taken with; otherwise reported as null.
-PMC_TRAFFIC = {"source_sha1": "af8a3056482fdf1ab59ac21d499a026843b0929d",
+PMC_TRAFFIC = {"source_sha1": "d93b20b153f4e605b04bda7d8c21f3a1c9c0988b",
                "n": 65536,
                "config": {"variant": 0, "block": 256, "splits": 32, "ilp": 1, "kahan_block": 8},
-               "fetch_kib": 4686.5, "write_kib": 49152.0, "fetch_scale": 2.0, "write_scale": 1.0}
+               "fetch_kib": 4683.3, "write_kib": 49152.0, "fetch_scale": 2.0, "write_scale": 1.0}
 
 
 def _measured_traffic(n, cfg):
