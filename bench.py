@@ -290,7 +290,7 @@ def run_lubrication(args, sd, W, dev):
     t_plain = _sync_time(lambda: sd.sd_run(x2, f4, 0.001, steps))
     fo = torch.empty_like(x)
     t_forces = _sync_time(lambda: [sd.lubrication_forces(x, vp, fd, fo) for _ in range(steps)])
-    roof = _pair_roofline(sd, n, lambda: sd.sd_run_lub(x, fd, vp, 0.001, 5))
+    roof = _pair_roofline(sd, n, lambda: sd.sd_run_lub(x, fd, vp, 0.001, 20))
     return {"metric": "Euler steps/s with lubrication at N=%d (FP32-comp pair kernel)" % n,
             "roofline": roof,
             "value": steps / t_lub, "unit": "steps/s", "n_gpus": 1, "higher_is_better": True,
@@ -340,7 +340,7 @@ def run_fcc(args, sd, W, dev):
         sd.sd_run(x, f4d, dt, 1, params=p, precision=sd.SD_FP64)
         t64 = _sync_time(lambda: sd.sd_run(x, f4d, dt, s64, params=p, precision=sd.SD_FP64))
         x.copy_(torch.tensor(x0, device=dev))
-        roof = _pair_roofline(sd, n, lambda: sd.sd_run(x, f4, dt, 5, params=p))
+        roof = _pair_roofline(sd, n, lambda: sd.sd_run(x, f4, dt, 20, params=p))
         row = {"m": m, "n": n, "box": L, "ms_per_step": t_plain * 1e3 / steps,
                "lubrication_step_ms": t_lub * 1e3 / steps,
                "ms_per_step_with_lubrication_step": (t_plain + t_lub) * 1e3 / steps,
