@@ -409,6 +409,22 @@ def run_precision(args, sd, W, dev):
         row = {"hi_accumulation": ACC_NAMES[a], "positions": POS_NAMES[p], "dt": dt,
                "cycles": int(len(dur)), "max_abs_y1": float(np.abs(xy[:, 1]).max())}
         if len(dur):
+            # Fig. 5: cycle duration and amplitude averaged over windows of 1e4 tau_s;
+            # the motion has broken down once a cycle deviates by more than 5 % from
+            # the first window's period
+            edges = np.arange(0.0, t[-1] + window, window)
+            wins = []
+            for lo_t in edges[:-1]:
+                sel = (tc >= lo_t) & (tc < lo_t + window)
+                sa = (ta >= lo_t) & (ta < lo_t + window)
+                if sel.any():
+                    wins.append([float(lo_t + window / 2), float(dur[sel].mean()),
+                                 float(amp[sa].mean()) if sa.any() else None])
+            row["windows_t_period_amplitude"] = wins
+            ref = dur[tc < tc[0] + window].mean()
+            bad = np.nonzero(np.abs(dur / ref - 1.0) > 0.05)[0]
+            row["breakdown_t"] = float(tc[bad[0]]) if len(bad) else None
+        if len(dur):
             first = dur[tc < tc[0] + window]
             last = dur[tc > tc[-1] - window]
             row.update({"period_first_window": float(first.mean()),
