@@ -303,7 +303,9 @@ typedef struct sd_cluster_spec {
  *          then of run 1, ...; run r writes floor(steps_r / stride_r) frames
  *          of 3n values, frame k being the positions after (k + 1) stride_r
  *          steps of this call.
- * The box of p must be zero (SD_EUNSUPPORTED otherwise).
+ * The box of p must be zero (SD_EUNSUPPORTED otherwise).  The run records
+ * are uploaded into library workspace and the call waits for `stream` once
+ * before launching (a long study calls it per chunk of millions of steps).
  */
 sd_status sd_cluster_run(const sd_params* p, int64_t n, int32_t runs, const sd_cluster_spec* specs,
                          double* state, const double* force, double* traj, void* stream);
