@@ -10,6 +10,7 @@
 // P = 256 / nc lanes per particle, each summing every P-th j; the P partial
 // velocities are combined in LDS in a fixed order.  Larger clusters (up to
 // SD_BATCH_MAX_CLUSTER) give each lane ceil(nc / 256) particles.
+#include "pair_terms.h"
 #include "sd.h"
 #include "sd_host.h"
 #include "sd_internal.h"
@@ -58,38 +59,6 @@ size_t batched_lds_bytes(int max_size, int precision, int integrator)
     return lds_layout(max_size, precision, integrator).total;
 }
 
-// FP64 near-pair contribution (same definitions as the product kernels).
-template <int TENSOR>
-__device__ __forceinline__ void b_near(const PairConst& pc, double d0, double d1, double d2,
-                                       double f0, double f1, double f2, double* nv)
-{
-    const double r2 = d0 * d0 + d1 * d1 + d2 * d2;
-    if (r2 == 0.0) {
-        if (TENSOR == T_RPY && pc.overlap) {
-            nv[0] += pc.mu0 * f0;
-            nv[1] += pc.mu0 * f1;
-            nv[2] += pc.mu0 * f2;
-        }
-        return;
-    }
-    const double r = sqrt(r2);
-    double cI, cD;
-    if (TENSOR == T_OSEEN) {
-        cI = pc.alpha / r;
-        cD = cI / r2;
-    } else if (pc.overlap && r < 2.0 * pc.a) {
-        cI = pc.mu0 * (1.0 - 9.0 * r / (32.0 * pc.a));
-        cD = pc.mu0 * 3.0 / (32.0 * pc.a * r);
-    } else {
-        const double ri = 1.0 / r, ri2 = ri * ri, ri3 = ri * ri2;
-        cI = pc.alpha * (ri + pc.gamma * ri3);
-        cD = pc.alpha * ri3 * (1.0 - 3.0 * pc.gamma * ri2);
-    }
-    const double dF = d0 * f0 + d1 * f1 + d2 * f2;
-    nv[0] += cI * f0 + cD * dF * d0;
-    nv[1] += cI * f1 + cD * dF * d1;
-    nv[2] += cI * f2 + cD * dF * d2;
-}
 
 // Velocity (pair part, physical units, self term excluded) of particle i from
 // the j = sub, sub + P, ... of the cluster held in LDS.
@@ -109,7 +78,7 @@ __device__ __forceinline__ void b_velocity(int i, int sub, int P, int nc, const 
             const double4 fj = fs[j];
             const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
             if (r2 < pc.thr2_d) {
-                if (j != i) b_near<TENSOR>(pc, dx, dy, dz, fj.x, fj.y, fj.z, nv);
+                if (j != i) near_term<TENSOR>(pc, dx, dy, dz, fj.x, fj.y, fj.z, nv[0], nv[1], nv[2]);
                 continue;
             }
             const double rinv = rsqrt(r2);
@@ -157,8 +126,8 @@ __device__ __forceinline__ void b_velocity(int i, int sub, int P, int nc, const 
             for (int u = 0; u < 4; ++u) {
                 const int jj = j + u * P;
                 if (r2[u] < thr2 && jj != i)
-                    b_near<TENSOR>(pc, xs[3 * i] - xs[3 * jj], xs[3 * i + 1] - xs[3 * jj + 1],
-                                   xs[3 * i + 2] - xs[3 * jj + 2], fj[u].x, fj[u].y, fj[u].z, nv);
+                    near_term<TENSOR>(pc, xs[3 * i] - xs[3 * jj], xs[3 * i + 1] - xs[3 * jj + 1],
+                                   xs[3 * i + 2] - xs[3 * jj + 2], fj[u].x, fj[u].y, fj[u].z, nv[0], nv[1], nv[2]);
                 r2[u] = (r2[u] < thr2) ? __builtin_inff() : r2[u];
             }
         }
@@ -198,8 +167,8 @@ __device__ __forceinline__ void b_velocity(int i, int sub, int P, int nc, const 
         const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
         if (r2 < thr2) {
             if (j != i)
-                b_near<TENSOR>(pc, xs[3 * i] - xs[3 * j], xs[3 * i + 1] - xs[3 * j + 1],
-                               xs[3 * i + 2] - xs[3 * j + 2], fj.x, fj.y, fj.z, nv);
+                near_term<TENSOR>(pc, xs[3 * i] - xs[3 * j], xs[3 * i + 1] - xs[3 * j + 1],
+                               xs[3 * i + 2] - xs[3 * j + 2], fj.x, fj.y, fj.z, nv[0], nv[1], nv[2]);
             continue;
         }
         const float rinv = __builtin_amdgcn_rsqf(r2);
