@@ -252,6 +252,27 @@ sd_status mobility_apply_batched(sd_batch* b, const void* pos, const void* force
 sd_status sd_run_batched(sd_batch* b, double* x, const void* force, double dt, int64_t steps,
                          int32_t integrator, int32_t precision, int32_t use_graph, void* stream);
 
+/*
+ * Shape of the persistent kernel of a plan: `workgroup` lanes per work-group
+ * (128, 256 or 512; 0 = the default 256) and `per_cu` resident work-groups
+ * per CU (0 = automatic: 1024 lanes per CU; at most 16; always limited by
+ * the 160 KiB of LDS per CU).  Changing it drops the plan's cached graph.
+ */
+sd_status sd_batch_set_config(sd_batch* b, int32_t workgroup, int32_t per_cu);
+sd_status sd_batch_get_config(const sd_batch* b, int32_t* workgroup, int32_t* per_cu);
+
+/*
+ * sd_batch_autotune -- times sd_run_batched(x, force, dt, steps, integrator,
+ * precision) for every work-group size (128, 256, 512) with three residency
+ * choices (automatic, half, double), each on a copy of x in library workspace
+ * (x is not modified; median of three launches after a warm-up), and keeps
+ * the fastest shape in the plan.  report (may be NULL) receives a JSON
+ * summary of every candidate.  Synchronous: returns after the timing.
+ */
+sd_status sd_batch_autotune(sd_batch* b, const double* x, const void* force, double dt,
+                            int64_t steps, int32_t integrator, int32_t precision, char* report,
+                            int64_t report_len, void* stream);
+
 /* ---------------------------------------------------------- precision study */
 
 /* Precision of the accumulation of the pair sum sum_{j != i} T(r_i - r_j) F_j

@@ -92,6 +92,10 @@ def lib() -> ctypes.CDLL:
             "sd_batch_destroy": [vp],
             "mobility_apply_batched": [vp, vp, vp, dp, i32, vp],
             "sd_run_batched": [vp, dp, vp, d, i64, i32, i32, i32, vp],
+            "sd_batch_set_config": [vp, i32, i32],
+            "sd_batch_get_config": [vp, ctypes.POINTER(ctypes.c_int32),
+                                    ctypes.POINTER(ctypes.c_int32)],
+            "sd_batch_autotune": [vp, dp, vp, d, i64, i32, i32, ctypes.c_char_p, i64, vp],
             "sd_set_kernel_config": [i32, ctypes.POINTER(SdKernelConfig)],
             "sd_get_kernel_config": [i32, i64, ctypes.POINTER(SdKernelConfig)],
             "sd_autotune": [P, i64, i32, vp, ctypes.c_char_p, i64],
@@ -326,6 +330,29 @@ class Batch:
                                     ctypes.byref(h)))
         self._h = h
         self.n = int(lib().sd_batch_particles(h))
+
+    def set_config(self, workgroup: int = 0, per_cu: int = 0) -> None:
+        """Persistent-kernel shape (sd_batch_set_config): lanes per
+        work-group 128 / 256 / 512 (0 = 256), work-groups per CU (0 = auto)."""
+        check(lib().sd_batch_set_config(self._h, int(workgroup), int(per_cu)))
+
+    def get_config(self) -> dict:
+        wg, pc = ctypes.c_int32(), ctypes.c_int32()
+        check(lib().sd_batch_get_config(self._h, ctypes.byref(wg), ctypes.byref(pc)))
+        return {"workgroup": wg.value, "per_cu": pc.value}
+
+    def autotune(self, x, force, dt: float, steps: int, *, integrator: int = SD_EULER,
+                 precision: int = None, stream=None) -> dict:
+        """Time every kernel shape on a copy of x and keep the fastest
+        (sd_batch_autotune); returns the JSON report as a dict."""
+        import json
+        prec = _default_precision(force) if precision is None else int(precision)
+        _vec3(x, self.n, "x")
+        _vec4(force, prec, "force")
+        buf = ctypes.create_string_buffer(8192)
+        check(lib().sd_batch_autotune(self._h, _ptr(x), _ptr(force), float(dt), int(steps),
+                                      int(integrator), prec, buf, len(buf), _stream(stream)))
+        return json.loads(buf.value.decode())
 
     def close(self):
         if self._h is not None and _lib is not None:

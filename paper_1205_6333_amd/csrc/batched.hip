@@ -2,14 +2,15 @@
 // its own (the mobility product of Eq. 7a restricted to a cluster, advanced by
 // the step loop of Sec. 3.1), in ONE persistent kernel launch.
 //
-// Each 256-lane work-group pulls cluster ids from a device work queue (an
-// atomic counter over a longest-first order prepared on the host), loads the
-// cluster into LDS (FP64 master positions, forces, FP32 staged positions) and
-// runs all time steps without leaving the kernel: clusters never interact, so
-// no grid-wide synchronisation is needed.  Clusters of nc <= 256 particles get
-// P = 256 / nc lanes per particle, each summing every P-th j; the P partial
-// velocities are combined in LDS in a fixed order.  Larger clusters (up to
-// SD_BATCH_MAX_CLUSTER) give each lane ceil(nc / 256) particles.
+// Each work-group of WG lanes (128, 256 or 512, chosen per plan, e.g. by the
+// autotuner) pulls cluster ids from a device work queue (an atomic counter
+// over a longest-first order prepared on the host), loads the cluster into LDS
+// (FP64 master positions, forces, FP32 staged positions) and runs all time
+// steps without leaving the kernel: clusters never interact, so no grid-wide
+// synchronisation is needed.  Clusters of nc <= WG particles get P = WG / nc
+// lanes per particle, each summing every P-th j; the P partial velocities are
+// combined in LDS in a fixed order.  Larger clusters (up to
+// SD_BATCH_MAX_CLUSTER) give each lane ceil(nc / WG) particles.
 #include "pair_terms.h"
 #include "sd.h"
 #include "sd_host.h"
@@ -18,26 +19,28 @@
 #include <algorithm>
 #include <cmath>
 #include <numeric>
+#include <cstdio>
+#include <string>
 #include <vector>
 
 namespace sd {
 
-constexpr int BB = 256;                          // lanes per work-group
-constexpr int MAX_ROWS = SD_BATCH_MAX_CLUSTER / BB;
 
 // LDS layout of one work-group (every segment 32-byte aligned):
 //   xs  f64[3M]   FP64 positions of the cluster
 //   fs  f32x4[M] or f64x4[M]   forces
 //   pf  f32x4[M]  FP32 staged positions (FP32 precisions)
 //   vp  f64[3M]   previous velocities (AB2)
-//   red f64[3*BB] per-lane partial velocities
+//   red f64[3*max(WG, M)] per-lane partial velocities (P > 1) or the
+//                 velocities of the cluster (one lane per particle)
 struct LdsLayout {
     size_t fs, pf, vp, red, total;
 };
 
 __host__ __device__ inline size_t lds_round(size_t b) { return (b + 31) & ~(size_t)31; }
 
-__host__ __device__ inline LdsLayout lds_layout(int max_size, int precision, int integrator)
+__host__ __device__ inline LdsLayout lds_layout(int max_size, int precision, int integrator,
+                                                int wg)
 {
     const size_t M = (size_t)max_size;
     LdsLayout L;
@@ -49,14 +52,14 @@ __host__ __device__ inline LdsLayout lds_layout(int max_size, int precision, int
     L.vp = o;
     if (integrator == SD_AB2) o += lds_round(M * 3 * sizeof(double));
     L.red = o;
-    o += lds_round((size_t)BB * 3 * sizeof(double));
+    o += lds_round((size_t)(wg > max_size ? wg : max_size) * 3 * sizeof(double));
     L.total = o;
     return L;
 }
 
-size_t batched_lds_bytes(int max_size, int precision, int integrator)
+size_t batched_lds_bytes(int max_size, int precision, int integrator, int wg)
 {
-    return lds_layout(max_size, precision, integrator).total;
+    return lds_layout(max_size, precision, integrator, wg).total;
 }
 
 
@@ -203,13 +206,14 @@ __device__ __forceinline__ void b_velocity(int i, int sub, int P, int nc, const 
 
 // RUN: `steps` steps per cluster, positions written back to x.
 // APPLY (steps < 0): one product, velocities written to vel.
-template <int TENSOR, int PREC, int INTEG>
-__global__ void __launch_bounds__(BB)
+template <int TENSOR, int PREC, int INTEG, int WG>
+__global__ void __launch_bounds__(WG)
 k_batched(BatchDev b, PairConst pc, double* __restrict__ x, const void* __restrict__ frc,
           double* __restrict__ vel, double dt, int steps)
 {
+    constexpr int BB = WG;
     extern __shared__ __align__(32) unsigned char lds[];
-    const LdsLayout lay = lds_layout(b.max_size, PREC, INTEG);
+    const LdsLayout lay = lds_layout(b.max_size, PREC, INTEG, WG);
     double* xs = (double*)lds;
     void* fs = lds + lay.fs;
     float4* pf = (PREC != SD_FP64) ? (float4*)(lds + lay.pf) : nullptr;
@@ -248,7 +252,7 @@ k_batched(BatchDev b, PairConst pc, double* __restrict__ x, const void* __restri
                     pf[k] = make_float4((float)xs[3 * k], (float)xs[3 * k + 1],
                                         (float)xs[3 * k + 2], 0.0f);
             __syncthreads();
-            double v[MAX_ROWS][3];
+            double v[3] = { 0.0, 0.0, 0.0 };  // P > 1: the owner's velocity
             if (P > 1) {
                 const int i = t / P, sub = t % P;
                 double w[3] = { 0.0, 0.0, 0.0 };
@@ -257,30 +261,33 @@ k_batched(BatchDev b, PairConst pc, double* __restrict__ x, const void* __restri
                 red[3 * t + 1] = w[1];
                 red[3 * t + 2] = w[2];
                 __syncthreads();
-                v[0][0] = v[0][1] = v[0][2] = 0.0;
                 if (sub == 0 && i < nc)
                     for (int u = 0; u < P; ++u) {
-                        v[0][0] += red[3 * (t + u)];
-                        v[0][1] += red[3 * (t + u) + 1];
-                        v[0][2] += red[3 * (t + u) + 2];
+                        v[0] += red[3 * (t + u)];
+                        v[1] += red[3 * (t + u) + 1];
+                        v[2] += red[3 * (t + u) + 2];
                     }
             } else {
-#pragma unroll
-                for (int r = 0; r < MAX_ROWS; ++r) {
+                // one lane per particle, rows of BB particles; velocities to LDS
+                for (int r = 0; r < rows; ++r) {
                     const int i = t + r * BB;
-                    v[r][0] = v[r][1] = v[r][2] = 0.0;
-                    if (r < rows && i < nc)
-                        b_velocity<TENSOR, PREC>(i, 0, 1, nc, xs, fs, pf, pc, v[r]);
+                    if (i >= nc) break;
+                    double w[3];
+                    b_velocity<TENSOR, PREC>(i, 0, 1, nc, xs, fs, pf, pc, w);
+                    red[3 * i] = w[0];
+                    red[3 * i + 1] = w[1];
+                    red[3 * i + 2] = w[2];
                 }
             }
-            __syncthreads();  // every read of xs / pf of this step is done
+            __syncthreads();  // every read of xs / pf / red of this step is done
             const int nrow = P > 1 ? 1 : rows;
-#pragma unroll
-            for (int r = 0; r < MAX_ROWS; ++r) {
-                if (r >= nrow) break;
+            for (int r = 0; r < nrow; ++r) {
                 const int i = (P > 1) ? t / P : t + r * BB;
                 const bool own = (P > 1) ? (t % P == 0 && i < nc) : (i < nc);
                 if (!own) continue;
+                const double w0 = P > 1 ? v[0] : red[3 * i];
+                const double w1 = P > 1 ? v[1] : red[3 * i + 1];
+                const double w2 = P > 1 ? v[2] : red[3 * i + 2];
                 double f0, f1, f2;
                 if (PREC == SD_FP64) {
                     const double4 f = ((const double4*)fs)[i];
@@ -289,8 +296,7 @@ k_batched(BatchDev b, PairConst pc, double* __restrict__ x, const void* __restri
                     const float4 f = ((const float4*)fs)[i];
                     f0 = f.x; f1 = f.y; f2 = f.z;
                 }
-                const double vv[3] = { pc.mu0 * f0 + v[r][0], pc.mu0 * f1 + v[r][1],
-                                       pc.mu0 * f2 + v[r][2] };
+                const double vv[3] = { pc.mu0 * f0 + w0, pc.mu0 * f1 + w1, pc.mu0 * f2 + w2 };
                 if (steps < 0) {
                     const size_t g = (size_t)(off + i);
                     vel[3 * g] = vv[0];
@@ -320,19 +326,31 @@ k_batched(BatchDev b, PairConst pc, double* __restrict__ x, const void* __restri
     }
 }
 
+template <int TENSOR, int PREC, int INTEG, int WG>
+static hipError_t launch_bw(const BatchDev& b, const PairConst& pc, double* x, const void* frc,
+                            double* vel, double dt, int steps, int nwg, hipStream_t st)
+{
+    const size_t lds = batched_lds_bytes(b.max_size, PREC, INTEG, WG);
+    if (lds > 64 * 1024) {
+        hipError_t e = hipFuncSetAttribute((const void*)k_batched<TENSOR, PREC, INTEG, WG>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL((k_batched<TENSOR, PREC, INTEG, WG>), dim3(nwg), dim3(WG), lds, st, b, pc,
+                       x, frc, vel, dt, steps);
+    return hipGetLastError();
+}
+
 template <int TENSOR, int PREC, int INTEG>
 static hipError_t launch_b(const BatchDev& b, const PairConst& pc, double* x, const void* frc,
                            double* vel, double dt, int steps, int nwg, hipStream_t st)
 {
-    const size_t lds = batched_lds_bytes(b.max_size, PREC, INTEG);
-    if (lds > 64 * 1024) {
-        hipError_t e = hipFuncSetAttribute((const void*)k_batched<TENSOR, PREC, INTEG>,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        if (e != hipSuccess) return e;
+    switch (b.wg) {
+    case 128: return launch_bw<TENSOR, PREC, INTEG, 128>(b, pc, x, frc, vel, dt, steps, nwg, st);
+    case 256: return launch_bw<TENSOR, PREC, INTEG, 256>(b, pc, x, frc, vel, dt, steps, nwg, st);
+    case 512: return launch_bw<TENSOR, PREC, INTEG, 512>(b, pc, x, frc, vel, dt, steps, nwg, st);
     }
-    hipLaunchKernelGGL((k_batched<TENSOR, PREC, INTEG>), dim3(nwg), dim3(BB), lds, st, b, pc, x,
-                       frc, vel, dt, steps);
-    return hipGetLastError();
+    return hipErrorInvalidValue;
 }
 
 template <int TENSOR>
@@ -409,11 +427,11 @@ struct GraphKey {
     const void* frc = nullptr;
     double dt = 0.0;
     int64_t steps = -1;
-    int32_t integ = -1, prec = -1, nwg = 0;
+    int32_t integ = -1, prec = -1, nwg = 0, wg = 0;
     bool operator==(const GraphKey& o) const
     {
         return x == o.x && frc == o.frc && dt == o.dt && steps == o.steps && integ == o.integ &&
-               prec == o.prec && nwg == o.nwg;
+               prec == o.prec && nwg == o.nwg && wg == o.wg;
     }
 };
 
@@ -425,6 +443,8 @@ struct sd_batch {
     int64_t n_clusters = 0;
     int64_t total = 0;
     int max_size = 0;
+    int wg = 256;               // lanes per work-group (128, 256, 512)
+    int per_cu = 0;             // resident work-groups per CU, 0 = automatic
     void* dmem = nullptr;       // offsets | order | counter
     int64_t* d_offsets = nullptr;
     int32_t* d_order = nullptr;
@@ -453,11 +473,15 @@ void batch_release_graphs()
     for (sd_batch* b : g_batches) drop_graph(b);
 }
 
+// Persistent grid: per_cu work-groups per CU (automatic: 1024 lanes per CU,
+// i.e. four waves per SIMD), limited by the 160 KiB of LDS per CU.
 static int batch_workgroups(const sd_batch* b, int prec, int integ)
 {
     const int cus = device_cus();
-    const size_t lds = batched_lds_bytes(b->max_size, prec, integ);
-    int per_cu = (int)std::min<size_t>(4, (160 * 1024) / std::max<size_t>(lds, 1));
+    const size_t lds = batched_lds_bytes(b->max_size, prec, integ, b->wg);
+    const int want_cu = b->per_cu > 0 ? b->per_cu : 1024 / b->wg;
+    int per_cu = (int)std::min<size_t>((size_t)want_cu,
+                                       (160 * 1024) / std::max<size_t>(lds, 1));
     per_cu = std::max(per_cu, 1);
     const int64_t want = (int64_t)cus * per_cu;
     return (int)std::max<int64_t>(1, std::min<int64_t>(want, b->n_clusters));
@@ -471,6 +495,7 @@ static BatchDev batch_dev(const sd_batch* b)
     d.counter = b->d_counter;
     d.n_clusters = (int)b->n_clusters;
     d.max_size = std::max(1, b->max_size);
+    d.wg = b->wg;
     return d;
 }
 
@@ -626,6 +651,7 @@ sd_status sd_run_batched(sd_batch* b, double* x, const void* force, double dt, i
     key.integ = integrator;
     key.prec = precision;
     key.nwg = nwg;
+    key.wg = b->wg;
     if (!b->exec || !(b->key == key)) {
         drop_graph(b);
         // capture [queue reset (fill kernel, no memset node), persistent kernel]
@@ -652,6 +678,106 @@ sd_status sd_run_batched(sd_batch* b, double* x, const void* force, double dt, i
         b->key = key;
     }
     if (hipGraphLaunch(b->exec, hs) != hipSuccess) return fail(SD_EDEVICE, "hipGraphLaunch failed");
+    return SD_OK;
+}
+
+sd_status sd_batch_set_config(sd_batch* b, int32_t workgroup, int32_t per_cu)
+{
+    sd_status st;
+    if ((st = check_batch(b))) return st;
+    if (workgroup == 0) workgroup = 256;
+    if (workgroup != 128 && workgroup != 256 && workgroup != 512)
+        return fail(SD_EINVAL, "workgroup must be 128, 256 or 512 (got %d)", workgroup);
+    if (per_cu < 0 || per_cu > 16) return fail(SD_EINVAL, "per_cu must be in [0, 16]");
+    if (b->wg != workgroup || b->per_cu != per_cu) drop_graph(b);
+    b->wg = workgroup;
+    b->per_cu = per_cu;
+    return SD_OK;
+}
+
+sd_status sd_batch_get_config(const sd_batch* b, int32_t* workgroup, int32_t* per_cu)
+{
+    sd_status st;
+    if ((st = check_batch(b))) return st;
+    if (!workgroup || !per_cu) return fail(SD_EINVAL, "output pointer is NULL");
+    *workgroup = b->wg;
+    *per_cu = b->per_cu;
+    return SD_OK;
+}
+
+sd_status sd_batch_autotune(sd_batch* b, const double* x, const void* force, double dt,
+                            int64_t steps, int32_t integrator, int32_t precision, char* report,
+                            int64_t report_len, void* stream)
+{
+    sd_status st;
+    if ((st = check_batch(b)) || (st = check_precision(precision))) return st;
+    if ((st = check_ptr(x, 8, "x")) || (st = check_ptr(force, vec4_align(precision), "force")))
+        return st;
+    if (!(dt > 0.0) || !std::isfinite(dt)) return fail(SD_EINVAL, "dt must be finite and > 0");
+    if (steps < 1 || steps > INT32_MAX) return fail(SD_EINVAL, "steps must be in [1, 2^31)");
+    if (integrator != SD_EULER && integrator != SD_AB2) return fail(SD_EINVAL, "unknown integrator");
+    hipStream_t hs = (hipStream_t)stream;
+    const size_t bytes = 3 * (size_t)b->total * sizeof(double);
+    void* scratch = nullptr;
+    if ((st = ws_get(WS_TUNE, bytes, &scratch))) return st;
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+        return fail(SD_EDEVICE, "hipEventCreate failed");
+    const int wg0 = b->wg, pc0 = b->per_cu;
+    struct Res {
+        int wg, per_cu;
+        float ms;
+    };
+    std::vector<Res> res;
+    const PairConst pc = pair_const(&b->p);
+    // every candidate runs the caller's steps on a copy of x (x is not changed):
+    // one warm-up, then the median of three timed launches
+    for (int wg : { 128, 256, 512 })
+        for (int pcu : { 0, 1, 2 }) {
+            const int per_cu = pcu == 0 ? 0 : (pcu == 1 ? 512 / wg : 2048 / wg);
+            if (per_cu > 16) continue;
+            b->wg = wg;
+            b->per_cu = per_cu;
+            const int nwg = batch_workgroups(b, precision, integrator);
+            const BatchDev d = batch_dev(b);
+            float t[4] = { 0.f, 0.f, 0.f, 0.f };
+            for (int r = 0; r < 4 && !st; ++r) {
+                hipError_t e = hipMemcpyAsync(scratch, x, bytes, hipMemcpyDeviceToDevice, hs);
+                if (e == hipSuccess) e = launch_fill_i32(b->d_counter, 0, 1, hs);
+                if (e == hipSuccess) e = hipEventRecord(e0, hs);
+                if (e == hipSuccess)
+                    e = launch_batched_run(d, b->p.tensor, precision, pc, (double*)scratch, force,
+                                           dt, (int)steps, integrator, nwg, hs);
+                if (e == hipSuccess) e = hipEventRecord(e1, hs);
+                if (e == hipSuccess) e = hipEventSynchronize(e1);
+                if (e == hipSuccess) e = hipEventElapsedTime(&t[r], e0, e1);
+                if (e != hipSuccess) st = fail(SD_EDEVICE, "batched autotune: %s",
+                                               hipGetErrorString(e));
+            }
+            if (st) break;
+            std::sort(t + 1, t + 4);
+            res.push_back({ wg, per_cu, t[2] });
+        }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    b->wg = wg0;
+    b->per_cu = pc0;
+    if (st) return st;
+    std::sort(res.begin(), res.end(), [](const Res& a, const Res& c) { return a.ms < c.ms; });
+    drop_graph(b);
+    b->wg = res[0].wg;
+    b->per_cu = res[0].per_cu;
+    if (report && report_len > 0) {
+        std::string js = "{\"best\": {\"workgroup\": " + std::to_string(res[0].wg) +
+                         ", \"per_cu\": " + std::to_string(res[0].per_cu) +
+                         ", \"ms\": " + std::to_string(res[0].ms) + "}, \"candidates\": [";
+        for (size_t k = 0; k < res.size(); ++k)
+            js += (k ? ", " : "") + std::string("{\"workgroup\": ") + std::to_string(res[k].wg) +
+                  ", \"per_cu\": " + std::to_string(res[k].per_cu) +
+                  ", \"ms\": " + std::to_string(res[k].ms) + "}";
+        js += "]}";
+        std::snprintf(report, (size_t)report_len, "%s", js.c_str());
+    }
     return SD_OK;
 }
 

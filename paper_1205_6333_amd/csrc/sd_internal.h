@@ -133,6 +133,7 @@ struct BatchDev {
     int32_t* counter;         // device, 1: work-queue head
     int n_clusters;
     int max_size;
+    int wg;                   // lanes per work-group: 128, 256 or 512
 };
 hipError_t launch_batched_run(const BatchDev& b, int tensor, int precision, const PairConst& pc,
                               double* x, const void* frc, double dt, int steps, int integrator,
@@ -142,6 +143,6 @@ hipError_t launch_batched_apply(const BatchDev& b, int tensor, int precision, co
                                 hipStream_t st);
 hipError_t launch_fill_i32(int32_t* p, int32_t value, int count, hipStream_t st);
 hipError_t launch_mean_vector(const double* v, int64_t n, double* out, hipStream_t st);
-size_t batched_lds_bytes(int max_size, int precision, int integrator);
+size_t batched_lds_bytes(int max_size, int precision, int integrator, int wg);
 
 }  // namespace sd

@@ -179,3 +179,13 @@ def test_membench_validation(L):
     assert L.sd_membench(0, 0, 0, (1 << 22) + 1, ok, ok, None) == b.SD_EINVAL
     assert L.sd_membench(0, 0, 1, 10, vp((1 << 20) + 4), ok, None) == b.SD_EALIGN
     assert L.sd_membench(0, 0, 0, 10, None, ok, None) == b.SD_EINVAL
+
+
+def test_batch_config_validation(L):
+    from paper_1205_6333_amd import binding as b
+    p = b.params()
+    h = ctypes.c_void_p()
+    assert L.sd_batch_set_config(None, 256, 0) == b.SD_EINVAL
+    wg, pc = ctypes.c_int32(), ctypes.c_int32()
+    assert L.sd_batch_get_config(None, ctypes.byref(wg), ctypes.byref(pc)) == b.SD_EINVAL
+    assert L.sd_batch_autotune(None, None, None, 0.1, 1, 0, 0, None, 0, None) == b.SD_EINVAL

@@ -183,3 +183,57 @@ def test_batched_full_workload_sampled_clusters(sd, orc):
     print("worst err/disp over %d clusters: %.3e" % (len(pick), worst))
     assert worst <= 1e-6
     b.close()
+
+
+@pytest.mark.parametrize("workgroup,per_cu", [(128, 0), (128, 16), (256, 2), (512, 0), (512, 1)])
+def test_kernel_shapes_vs_oracle(sd, orc, workgroup, per_cu):
+    """Every work-group size and residency of the persistent kernel, on
+    clusters that use both the several-lanes-per-particle and the
+    rows-of-particles mappings (sizes 1 ... 1024), FP32-comp and FP64."""
+    import torch
+    sizes = [1, 3, 7, 60, 64, 65, 127, 128, 129, 200, 256, 300, 511, 512, 513, 1024, 2]
+    rng = np.random.default_rng(21)
+    xs = [W._sequential_reject(lambda k: rng.normal(0, 6.0, size=(k, 3)), s, 2.2, batch=64)
+          for s in sizes]
+    offsets = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    x = np.concatenate(xs, 0)
+    f = W.gravity_forces(len(x)) + 0.2 * W.gaussian_forces(len(x), seed=22)
+    b = sd.Batch(offsets)
+    b.set_config(workgroup, per_cu)
+    assert b.get_config() == {"workgroup": workgroup, "per_cu": per_cu}
+    p = orc.params()
+    for prec, tol in ((0, 1e-6), (1, 1e-12)):
+        fo = f if prec == 1 else W.round_to_f32(f)
+        xo = x if prec == 1 else W.round_to_f32(x)
+        v = sd.mobility_apply_batched(b, to_dev4(xo, _dt(sd, prec)), to_dev4(fo, _dt(sd, prec)),
+                                      precision=prec)
+        xd = to_dev3(x)
+        sd.sd_run_batched(b, xd, to_dev4(fo, _dt(sd, prec)), 0.02, 8, precision=prec,
+                          integrator=1, use_graph=True)
+        torch.cuda.synchronize()
+        ref_v = _per_cluster(offsets, lambda a, e: orc.mobility(p, xo[a:e], fo[a:e]))
+        assert rel2(v.cpu().numpy(), ref_v) <= tol
+        ref_x = _per_cluster(offsets, lambda a, e: orc.run(p, x[a:e], fo[a:e], 0.02, 8, 1)[0])
+        assert np.abs(xd.cpu().numpy() - ref_x).max() <= tol * 100 * np.abs(ref_x - x).max()
+    b.close()
+
+
+def test_batched_autotune_keeps_the_fastest_shape(sd, orc, clusters):
+    import torch
+    offsets, x, f = clusters
+    b = sd.Batch(offsets)
+    xd = to_dev3(x)
+    frc = to_dev4(W.round_to_f32(f), torch.float32)
+    rep = b.autotune(xd, frc, 0.01, 20)
+    assert torch.equal(xd, to_dev3(x))                 # x is not changed
+    cands = rep["candidates"]
+    assert len(cands) >= 7
+    best = min(cands, key=lambda c: c["ms"])
+    assert b.get_config() == {"workgroup": best["workgroup"], "per_cu": best["per_cu"]}
+    sd.sd_run_batched(b, xd, frc, 0.01, 20)
+    torch.cuda.synchronize()
+    p = orc.params()
+    fo = W.round_to_f32(f)
+    ref = _per_cluster(offsets, lambda a, e: orc.run(p, x[a:e], fo[a:e], 0.01, 20)[0])
+    assert np.abs(xd.cpu().numpy() - ref).max() <= 1e-6 * np.abs(ref - x).max()
+    b.close()
