@@ -54,7 +54,6 @@ import numpy as np
 
 FLOP_PER_PAIR = 35          # canonical useful flops per pair, see the design doc
 PEAK_FP32_TFLOPS = 157.3    # MI355X published FP32 vector peak
-PEAK_FP32_NONPACKED = 78.6  # the same without packed FP32 (256 CU x 4 SIMD x 16 lanes x 2 x 2.4 GHz)
 METRIC = "G pair-interactions/s of RPY mobility product at N=65536 (FP32-comp vs FP64)"
 
 # HBM traffic of one product-kernel launch from two rocprofv3 counter passes
@@ -81,6 +80,19 @@ def _measured_traffic(n, cfg):
     if sha != m["source_sha1"] or n != m["n"] or dict(cfg) != m["config"]:
         return None
     return 1024.0 * (m["fetch_kib"] * m["fetch_scale"] + m["write_kib"] * m["write_scale"])
+
+
+# VALU wave instructions of one product-kernel launch (rocprofv3 SQ_INSTS_VALU,
+# profiles/pair_kernel_f32_n65536_valu_counters.md), same validity rule.
+PMC_VALU = {"source_sha1": PMC_TRAFFIC["source_sha1"], "n": 65536,
+            "config": PMC_TRAFFIC["config"], "valu_wave_instr": 1634484224}
+
+
+def _measured_valu(n, cfg):
+    """VALU lane-instructions per launch, or None if the counters are stale."""
+    if _measured_traffic(n, cfg) is None or PMC_VALU["n"] != n or dict(cfg) != PMC_VALU["config"]:
+        return None
+    return 64.0 * PMC_VALU["valu_wave_instr"]
 
 
 def _to4(v, dtype, device):
@@ -268,7 +280,6 @@ def _pair_roofline(sd, n, fn):
     achieved = FLOP_PER_PAIR * float(n) * n / (kern_ms * 1e-3) / 1e12
     return {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
             "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None,
-            "frac_of_nonpacked_peak": achieved / PEAK_FP32_NONPACKED,
             "kernel": "pair kernel", "pair_kernel_ms": kern_ms, "launches": launches}
 
 
@@ -583,8 +594,11 @@ def main():
                        "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_TFLOPS,
                        "traffic": _measured_traffic(n, cfg),
                        "flop_per_pair": FLOP_PER_PAIR,
-                       "frac_of_nonpacked_peak": achieved / PEAK_FP32_NONPACKED,
                        "kernel": "pair kernel (k_pair_f32_*)"}
+    valu = _measured_valu(n, cfg)
+    if valu is not None:
+        out["roofline"]["valu_lane_instr_per_pair"] = valu / pairs
+        out["roofline"]["valu_t_lane_instr_per_s"] = valu / (kern_ms * 1e-3) / 1e12
     if not args.no_fp64:
         pos64, frc64 = _to4(x, torch.float64, dev), _to4(f, torch.float64, dev)
         vel64 = torch.empty((n, 3), dtype=torch.float64, device=dev)
