@@ -428,6 +428,10 @@ sd_status sd_pack(int64_t n, const double* v, void* out, int32_t precision, void
 sd_status sd_release(void);
 const char* sd_status_string(int32_t status);
 const char* sd_last_error(void);
+/* 100 * major + minor; 110 added the periodic box (sd_params.box), the
+ * lubrication entry points, the precision study, the micro-benchmarks and the
+ * batched-kernel shape. */
+#define SD_VERSION 110
 int32_t sd_version(void);
 
 #ifdef __cplusplus

@@ -596,7 +596,7 @@ const char* sd_last_error(void)
 
 int32_t sd_version(void)
 {
-    return 100;
+    return SD_VERSION;
 }
 
 }  // extern "C"
