@@ -119,3 +119,26 @@ def test_run_lub_hard_core(sd):
                       precision=sd.SD_FP32_KAHAN)
         gaps.append(float(torch.linalg.norm(x[0] - x[1])))
     assert min(gaps) > 2.0
+
+
+def test_lubrication_full_size_sampled(sd, orc):
+    """The N = 65536 suspension of the lubrication benchmark (phi = 0.05, gaps
+    >= 0.6a) with a random velocity field: the forces on 64 sampled particles
+    against the oracle run on their neighbourhoods (every particle within the
+    cutoff 3a of a sampled one; the truncated Eq. 8 sees nothing farther)."""
+    import torch
+    from scipy.spatial import cKDTree
+    n = 65536
+    x = W.random_suspension(n, phi=0.05, min_dist=2.6, seed=1)
+    v = W.gaussian_forces(n, seed=5)
+    got = _forces(sd, x, v, None, sd.lub(), sd.params())
+    rows = np.random.default_rng(14).choice(n, 64, replace=False)
+    tree = cKDTree(x)
+    po, lo = orc.params(), orc.lub()
+    active = 0
+    for i in rows:
+        nb = np.array(sorted(tree.query_ball_point(x[i], 3.0 * (1 + 1e-9))))
+        ref = orc.lubrication_force(po, lo, x[nb], v[nb])[np.searchsorted(nb, i)]
+        active += np.any(ref != 0)
+        assert np.abs(got[i] - ref).max() <= 1e-12 * max(1.0, np.abs(ref).max())
+    assert active >= 10

@@ -189,3 +189,20 @@ def test_periodic_run_lub_parity(sd, orc, prec):
     err = np.abs(xd.cpu().numpy() - xr).max() / np.abs(xr - x0).max()
     print("prec=%d err/disp=%.3e" % (prec, err))
     assert err <= (1e-11 if prec == 1 else 1e-6)
+
+
+def test_fcc_full_size_sampled(sd, orc):
+    """The largest size of the fcc benchmark (m = 37, N = 202612) in its launch
+    configuration, jittered so that every nearest image is unique: 48 sampled
+    rows of the FP32-compensated product against the oracle."""
+    import torch
+    x, L = W.jittered_fcc(37, jitter=0.05, seed=370)
+    n = len(x)
+    f = W.gravity_forces(n) + 0.1 * W.gaussian_forces(n, seed=371)
+    x32, f32 = W.round_to_f32(x), W.round_to_f32(f)
+    v = _apply(sd, x32, f32, 0, sd.params(box=L))
+    rows = np.random.default_rng(372).choice(n, 48, replace=False)
+    ref = orc.mobility_rows(orc.params(box=L), x32, f32, rows)
+    err = rel2(v[rows], ref)
+    print("fcc N=%d sampled rel2 = %.3e" % (n, err))
+    assert err <= 1e-6
