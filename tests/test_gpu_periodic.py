@@ -206,3 +206,24 @@ def test_fcc_full_size_sampled(sd, orc):
     err = rel2(v[rows], ref)
     print("fcc N=%d sampled rel2 = %.3e" % (n, err))
     assert err <= 1e-6
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_small_and_large_boxes(sd, orc, prec):
+    """A box just larger than a sphere diameter (every pair near contact or
+    overlapping through some image; overlap-regularised RPY) and a box far
+    larger than the suspension (the nearest image is the free-space pair)."""
+    rng = np.random.default_rng(380)
+    L = 3.0
+    x = rng.uniform(0.0, L, size=(7, 3))
+    f = rng.standard_normal((7, 3))
+    ps = sd.params(overlap=True, box=L)
+    po = orc.params(overlap=True, box=L)
+    v = _apply(sd, x, f, prec, ps)
+    ref = orc.mobility(po, _in(x, prec), _in(f, prec))
+    assert rel2(v, ref) <= TOL[prec]
+    x = W.random_suspension(500, phi=0.05, seed=381) + 100.0
+    f = W.gaussian_forces(500, seed=382)
+    v = _apply(sd, x, f, prec, sd.params(box=2000.0))
+    ref = orc.mobility(orc.params(), _in(x, prec), _in(f, prec))   # free space
+    assert rel2(v, ref) <= TOL[prec]

@@ -110,3 +110,19 @@ def test_periodic_adjoint_and_symmetry(orc):
             fd[i, k] = (np.sum(lam * orc.mobility(p, xp, f)) -
                         np.sum(lam * orc.mobility(p, xm, f))) / (2 * h)
     np.testing.assert_allclose(g, fd, rtol=1e-6, atol=1e-8 * np.abs(g).max())
+
+
+def test_periodic_input_generators():
+    """Inputs of the periodic tests: the periodic RSA keeps the nearest-image
+    distance, the jittered lattice lies in [0, L) and has no pair exactly half
+    a box apart along any axis (its nearest images are unique)."""
+    x, L = W.periodic_suspension(400, phi=0.2, min_dist=2.1, seed=5)
+    d = x[:, None] - x[None]
+    d -= L * np.rint(d / L)
+    r = np.sqrt((d ** 2).sum(-1))
+    np.fill_diagonal(r, np.inf)
+    assert r.min() >= 2.1 and x.min() >= 0 and x.max() < L
+    xj, Lj = W.jittered_fcc(4, jitter=0.05, seed=6)
+    assert xj.min() >= 0 and xj.max() < Lj
+    dj = np.abs(xj[:, None] - xj[None])
+    assert np.abs(dj - Lj / 2).min() > 1e-6
