@@ -163,6 +163,19 @@ sd_status sd_run(const sd_params* p, int64_t n, double* x, const void* force, do
                  double* x_checkpoints, int64_t checkpoint_every, void* stream);
 
 /*
+ * sd_set_graph_mode -- how sd_run launches its steps when no checkpoints are
+ * requested and profiling is off: 0 = every kernel launched on the stream;
+ * 1 (default) = for n <= 16384, where a step is launch-bound, chunks of 16
+ * steps are captured once into a HIP graph (on a private capture stream,
+ * kernel nodes only) and replayed on the caller's stream; 2 = graphs at every
+ * n.  The results are identical in every mode (the same kernels in the same
+ * order).  The captured graph is cached per device and rebuilt when any
+ * argument, size, parameter, kernel shape or workspace it captured changes;
+ * sd_release frees it.
+ */
+sd_status sd_set_graph_mode(int32_t mode);
+
+/*
  * sd_run_adjoint -- gradients of a loss L(x_steps) through `steps` Euler steps
  * started at x0 (discrete adjoint of sd_run with SD_EULER, step0 = 0):
  *   lam_steps = grad_xN;  lam_k = lam_{k+1} + dt d/dx[lam_{k+1} . M(x_k) F]

@@ -18,3 +18,4 @@ from .binding import (SD_ACC_DS, SD_ACC_FP32, SD_ACC_FP64, SD_ACC_KAHAN, SD_POS_
                       SD_POS_FP32, SD_POS_FP64, cluster_frames, sd_cluster_run)
 from .binding import (SD_MB_LINEAR, SD_MB_NAIVE, SD_MB_SMALLTILING, SD_MB_STRIDED,  # noqa: E402,F401
                       SD_MB_TILING, SD_MB_UNORDERED, sd_membench)
+from .binding import sd_set_graph_mode  # noqa: E402,F401

@@ -103,6 +103,7 @@ def lib() -> ctypes.CDLL:
             "lubrication_forces": [P, ctypes.POINTER(SdLub), i64, dp, dp, dp, dp, vp],
             "sd_run_lub": [P, ctypes.POINTER(SdLub), i64, dp, dp, dp, d, i64, i64, i32, i32, vp],
             "sd_mean_vector": [i64, dp, dp, vp],
+            "sd_set_graph_mode": [i32],
             "sd_cluster_run": [P, i64, i32, ctypes.POINTER(SdClusterSpec), dp, dp, dp, vp],
             "sd_membench": [i32, i32, i32, i64, vp, vp, vp],
             "sd_profile_enable": [i32],
@@ -442,6 +443,11 @@ def sd_membench(kind: int, access: int, inp, out=None, stream=None):
     check(lib().sd_membench(int(kind), int(access), elem, inp.shape[0], _ptr(inp), _ptr(out),
                             _stream(stream)))
     return out
+
+
+def sd_set_graph_mode(mode: int) -> None:
+    """sd_run launch mode: 0 eager, 1 graphs for small n (default), 2 graphs always."""
+    check(lib().sd_set_graph_mode(int(mode)))
 
 
 def sd_pack(v, precision: int = SD_FP32_KAHAN, out=None, stream=None):

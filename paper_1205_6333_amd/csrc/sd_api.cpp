@@ -340,6 +340,67 @@ size_t partial_bytes(const PairLaunch& L, int64_t n)
 
 }  // namespace sd
 
+// ------------------------------------------------------- graph-captured loop
+//
+// The time loop of sd_run is launch-bound for small n (two short kernels per
+// step).  Chunks of RUN_CHUNK steps [stage, (pair kernel, merge + integrate
+// + staging) x RUN_CHUNK] are captured once into a HIP graph on a private
+// capture stream and replayed on the caller's stream; a chunk holds only
+// kernel nodes.  The graph is cached per device and rebuilt when anything it
+// captured changes (pointers, sizes, parameters, launch shape, workspace).
+namespace {
+
+constexpr int RUN_CHUNK = 16;
+
+struct RunKey {
+    sd_params p{};
+    int64_t n = 0;
+    double* x = nullptr;
+    const void* force = nullptr;
+    double* v_prev = nullptr;
+    double dt = 0.0;
+    int32_t integ = -1, mode = -1, prec = -1;
+    sd::PairLaunch L{};
+    void* partial = nullptr;
+    void* stage = nullptr;
+    bool operator==(const RunKey& o) const { return std::memcmp(this, &o, sizeof(RunKey)) == 0; }
+};
+
+struct RunGraph {
+    RunKey key;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hipStream_t cap = nullptr;
+};
+
+std::mutex g_rg_mu;
+std::map<int, RunGraph> g_rg;
+int32_t g_graph_mode = 1;   // 0 off, 1 automatic (n <= RUN_GRAPH_AUTO_N), 2 always
+constexpr int64_t RUN_GRAPH_AUTO_N = 16384;
+
+void drop_run_graph(RunGraph& g)
+{
+    if (g.exec) (void)hipGraphExecDestroy(g.exec);
+    if (g.graph) (void)hipGraphDestroy(g.graph);
+    g.exec = nullptr;
+    g.graph = nullptr;
+    g.key = RunKey();
+}
+
+}  // namespace
+
+namespace sd {
+void run_graphs_release()
+{
+    std::lock_guard<std::mutex> lk(g_rg_mu);
+    for (auto& kv : g_rg) {
+        drop_run_graph(kv.second);
+        if (kv.second.cap) (void)hipStreamDestroy(kv.second.cap);
+        kv.second.cap = nullptr;
+    }
+}
+}  // namespace sd
+
 using namespace sd;
 
 // ====================================================================== ABI
@@ -466,9 +527,67 @@ sd_status sd_run(const sd_params* p, int64_t n, double* x, const void* force, do
         (st = ws_get(WS_STAGE, (size_t)n * (precision == SD_FP64 ? 32 : 16), &stage)))
         return st;
     double* vp = integrator == SD_AB2 ? v_prev : nullptr;
-    for (int64_t s = 0; s < steps; ++s) {
+    int64_t done = 0;
+    const bool graphed = !x_checkpoints && !g_prof.on && steps >= 2 * RUN_CHUNK &&
+                         (g_graph_mode == 2 || (g_graph_mode == 1 && n <= RUN_GRAPH_AUTO_N));
+    if (graphed) {
+        // the first AB2 step (an Euler step that stores v_prev) stays eager
+        if (integrator == SD_AB2 && step0 == 0) {
+            if ((st = step_impl(p, n, x, force, vp, nullptr, dt, 0, integrator, precision, stage,
+                                false, false, (double*)partial, L, hs)))
+                return st;
+            done = 1;
+        }
+        int dev = 0;
+        if (hipGetDevice(&dev) != hipSuccess) return fail(SD_EDEVICE, "hipGetDevice failed");
+        RunKey key;
+        std::memset(&key, 0, sizeof key);
+        key.p = *p;
+        key.n = n;
+        key.x = x;
+        key.force = force;
+        key.v_prev = vp;
+        key.dt = dt;
+        key.integ = integrator;
+        key.mode = integrator == SD_EULER ? 0 : 2;
+        key.prec = precision;
+        key.L = L;
+        key.partial = partial;
+        key.stage = stage;
+        std::lock_guard<std::mutex> lk(g_rg_mu);
+        RunGraph& g = g_rg[dev];
+        if (!g.cap && hipStreamCreateWithFlags(&g.cap, hipStreamNonBlocking) != hipSuccess)
+            return fail(SD_EDEVICE, "capture stream creation failed");
+        if (!g.exec || !(g.key == key)) {
+            drop_run_graph(g);
+            if (hipStreamBeginCapture(g.cap, hipStreamCaptureModeThreadLocal) != hipSuccess)
+                return fail(SD_EDEVICE, "hipStreamBeginCapture failed");
+            sd_status cst = SD_OK;
+            for (int k = 0; k < RUN_CHUNK && !cst; ++k)   // step index 1: never the AB2 start
+                cst = step_impl(p, n, x, force, vp, nullptr, dt, 1, integrator, precision, stage,
+                                k > 0, k + 1 < RUN_CHUNK, (double*)partial, L, g.cap);
+            hipGraph_t graph = nullptr;
+            const hipError_t e2 = hipStreamEndCapture(g.cap, &graph);
+            if (cst || e2 != hipSuccess || !graph) {
+                if (graph) (void)hipGraphDestroy(graph);
+                return cst ? cst : fail(SD_EDEVICE, "graph capture failed: %s", hipGetErrorString(e2));
+            }
+            hipGraphExec_t exec = nullptr;
+            if (hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) != hipSuccess) {
+                (void)hipGraphDestroy(graph);
+                return fail(SD_EDEVICE, "hipGraphInstantiate failed");
+            }
+            g.graph = graph;
+            g.exec = exec;
+            g.key = key;
+        }
+        for (; done + RUN_CHUNK <= steps; done += RUN_CHUNK)
+            if (hipGraphLaunch(g.exec, hs) != hipSuccess)
+                return fail(SD_EDEVICE, "hipGraphLaunch failed");
+    }
+    for (int64_t s = done; s < steps; ++s) {
         if ((st = step_impl(p, n, x, force, vp, nullptr, dt, step0 + s, integrator, precision, stage,
-                            s > 0, s + 1 < steps, (double*)partial, L, hs)))
+                            s > done, s + 1 < steps, (double*)partial, L, hs)))
             return st;
         if (x_checkpoints && (s + 1) % checkpoint_every == 0) {
             double* dst = x_checkpoints + 3 * (size_t)n * (size_t)((s + 1) / checkpoint_every);
@@ -570,9 +689,17 @@ sd_status sd_profile_reset(void)
     return SD_OK;
 }
 
+sd_status sd_set_graph_mode(int32_t mode)
+{
+    if (mode < 0 || mode > 2) return fail(SD_EINVAL, "graph mode must be 0, 1 or 2");
+    g_graph_mode = mode;
+    return SD_OK;
+}
+
 sd_status sd_release(void)
 {
     batch_release_graphs();
+    run_graphs_release();
     return ws_release_all();
 }
 

@@ -54,5 +54,6 @@ sd_status run_pair(const sd_params* p, int64_t n, const void* pos, const void* f
                    hipStream_t st);
 
 void batch_release_graphs();
+void run_graphs_release();
 
 }  // namespace sd

@@ -144,3 +144,37 @@ def test_sedimentation_full_size_two_steps(sd, orc):
         print("prec=%d 2-step err/disp=%.3e" % (prec, err))
         assert err <= tol
         np.testing.assert_allclose(vcm.cpu().numpy(), vr.mean(0), rtol=10 * tol)
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("integ,steps,step0", [(0, 5, 0), (0, 37, 0), (1, 100, 0), (1, 50, 7)])
+def test_graph_replays_match_eager(sd, prec, integ, steps, step0):
+    """sd_run replays captured chunks of 16 steps: bitwise the eager loop, over
+    several replays with eager work and synchronisations between them, with a
+    periodic box too (a different captured graph)."""
+    import torch
+    n = 1000
+    x0 = W.random_suspension(n, phi=0.05, seed=40)
+    f = W.gravity_forces(n) + 0.2 * W.gaussian_forces(n, seed=41)
+    dt4 = torch.float64 if prec == 1 else torch.float32
+    frc = to_dev4(f, dt4)
+    vp0 = to_dev3(W.gaussian_forces(n, seed=42))
+    for p in (sd.params(overlap=True), sd.params(box=60.0)):
+        sd.sd_set_graph_mode(0)
+        xe, ve = to_dev3(x0), vp0.clone()
+        sd.sd_run(xe, frc, 0.01, steps, step0=step0, v_prev=ve, integrator=integ, params=p,
+                  precision=prec)
+        sd.sd_set_graph_mode(2)
+        try:
+            for rep in range(3):
+                xg, vg = to_dev3(x0), vp0.clone()
+                torch.cuda.synchronize()
+                sd.sd_run(xg, frc, 0.01, steps, step0=step0, v_prev=vg, integrator=integ,
+                          params=p, precision=prec)
+                scratch = torch.randn(4096, device=xg.device).sum()   # unrelated eager work
+                torch.cuda.synchronize()
+                assert torch.equal(xg, xe), rep
+                assert torch.equal(vg, ve) or integ == 0, rep
+                assert torch.isfinite(scratch)
+        finally:
+            sd.sd_set_graph_mode(1)
