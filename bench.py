@@ -341,7 +341,7 @@ def run_fcc(args, sd, W, dev):
         f4 = _to4(f, torch.float32, dev)
         f4d = _to4(f, torch.float64, dev)
         x = torch.tensor(x0, device=dev)
-        sd.sd_run(x, f4, dt, 3, params=p)                 # warm-up
+        sd.sd_run(x, f4, dt, steps, params=p)             # warm-up (captures the step graph)
         x.copy_(torch.tensor(x0, device=dev))
         t_plain = _sync_time(lambda: sd.sd_run(x, f4, dt, steps, params=p))
         v = sd.mobility_apply(_to4(x.cpu().numpy(), torch.float32, dev), f4, params=p)
@@ -351,7 +351,8 @@ def run_fcc(args, sd, W, dev):
                                     for _ in range(steps)])
         s64 = steps if n <= 65536 else 10
         x.copy_(torch.tensor(x0, device=dev))
-        sd.sd_run(x, f4d, dt, 1, params=p, precision=sd.SD_FP64)
+        sd.sd_run(x, f4d, dt, s64, params=p, precision=sd.SD_FP64)
+        x.copy_(torch.tensor(x0, device=dev))
         t64 = _sync_time(lambda: sd.sd_run(x, f4d, dt, s64, params=p, precision=sd.SD_FP64))
         x.copy_(torch.tensor(x0, device=dev))
         roof = _pair_roofline(sd, n, lambda: sd.sd_run(x, f4, dt, 20, params=p))
