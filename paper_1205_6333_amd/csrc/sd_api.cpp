@@ -197,10 +197,12 @@ sd_kernel_config default_config(int32_t prec, int64_t n)
 {
     sd_kernel_config c;
     c.variant = 0;
-    // Small n cannot fill the chip with 256-lane groups (an i-block and a j-tile
-    // per work-group): narrower groups give (n / block)^2 work-groups.  The
-    // Kahan block of 8 needs groups of at least 128 lanes.
-    c.block = n >= 16384 ? 256 : (n >= 4096 ? 128 : 64);
+    // Below n = 4096, 256-lane groups (an i-block and a j-tile per work-group)
+    // cannot fill the chip: 64-lane groups give 16x as many.  (Measured on the
+    // fcc start: n = 256 0.024 -> 0.014 ms per step, n = 2048 0.027 -> 0.024;
+    // at n = 5324 128-lane groups were slower than 256.)  The Kahan block of 8
+    // needs groups of at least 128 lanes.
+    c.block = n >= 4096 ? 256 : 64;
     c.ilp = 1;
     c.kahan_block = (prec == SD_FP32_PLAIN) ? 0 : (c.block >= 128 ? 8 : 4);
     if (prec == SD_FP64) {
