@@ -6,7 +6,8 @@ does, and this package never imports the GPU library: the two share no code.
 
 The arithmetic lives in ``sd_oracle.c`` (plain double loops, see the comments
 there for the equation each function follows).  This module compiles it with
-gcc and wraps it for numpy arrays of shape (n, 3), float64.
+gcc and wraps it for numpy arrays of shape (n, 3), float64.  ``membench.py``
+holds the (numpy) oracle of the App. A memory-access benchmarks.
 """
 from __future__ import annotations
 

@@ -28,7 +28,9 @@
  *   - lubrication (Eq. 8): the surface separation s = r/a - 2 is clamped below
  *     at s_min (the paper does not say what happens at contact or overlap),
  *     and the previous step's velocities are supplied by the caller (zero or
- *     any other initial guess before the first step).
+ *     any other initial guess before the first step);
+ *   - periodic box (footnote of Sec. 3.1): only the nearest image interacts;
+ *     a difference of exactly half a box rounds half to even (nearbyint).
  */
 #include <math.h>
 #ifdef _OPENMP
