@@ -453,14 +453,17 @@ struct sd_batch {
     sd::GraphKey key;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
+    hipEvent_t done = nullptr;  // recorded after the last replay
 };
 
 namespace sd {
 
 static std::vector<sd_batch*> g_batches;
 
+// Waits for the last replay before the executable graph is destroyed.
 static void drop_graph(sd_batch* b)
 {
+    if (b->exec && b->done) (void)hipEventSynchronize(b->done);
     if (b->exec) (void)hipGraphExecDestroy(b->exec);
     if (b->graph) (void)hipGraphDestroy(b->graph);
     b->exec = nullptr;
@@ -565,7 +568,9 @@ sd_status sd_batch_create(const sd_params* p, int64_t n_clusters, const int64_t*
     b->d_counter = (int32_t*)((char*)b->dmem + ((ob + rb + 63) & ~(size_t)63));
     if (hipMemcpy(b->d_offsets, offsets, ob, hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(b->d_order, order.data(), rb, hipMemcpyHostToDevice) != hipSuccess ||
-        hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking) != hipSuccess) {
+        hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&b->done, hipEventDisableTiming) != hipSuccess) {
+        if (b->cap) (void)hipStreamDestroy(b->cap);
         (void)hipFree(b->dmem);
         delete b;
         return fail(SD_EDEVICE, "plan upload failed");
@@ -581,6 +586,7 @@ sd_status sd_batch_destroy(sd_batch* b)
     (void)hipDeviceSynchronize();
     drop_graph(b);
     if (b->cap) (void)hipStreamDestroy(b->cap);
+    if (b->done) (void)hipEventDestroy(b->done);
     if (b->dmem) (void)hipFree(b->dmem);
     g_batches.erase(std::remove(g_batches.begin(), g_batches.end(), b), g_batches.end());
     delete b;
@@ -678,6 +684,7 @@ sd_status sd_run_batched(sd_batch* b, double* x, const void* force, double dt, i
         b->key = key;
     }
     if (hipGraphLaunch(b->exec, hs) != hipSuccess) return fail(SD_EDEVICE, "hipGraphLaunch failed");
+    if (hipEventRecord(b->done, hs) != hipSuccess) return fail(SD_EDEVICE, "event record failed");
     return SD_OK;
 }
 

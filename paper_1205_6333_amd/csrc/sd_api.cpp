@@ -376,6 +376,7 @@ struct RunGraph {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     hipStream_t cap = nullptr;
+    hipEvent_t done = nullptr;  // recorded after the last replay
 };
 
 std::mutex g_rg_mu;
@@ -383,8 +384,11 @@ std::map<int, RunGraph> g_rg;
 int32_t g_graph_mode = 1;   // 0 off, 1 automatic (n <= RUN_GRAPH_AUTO_N), 2 always
 constexpr int64_t RUN_GRAPH_AUTO_N = 16384;
 
+// Waits for the last replay before the executable graph is destroyed (a
+// rebuild may come from a call on another stream).
 void drop_run_graph(RunGraph& g)
 {
+    if (g.exec && g.done) (void)hipEventSynchronize(g.done);
     if (g.exec) (void)hipGraphExecDestroy(g.exec);
     if (g.graph) (void)hipGraphDestroy(g.graph);
     g.exec = nullptr;
@@ -401,7 +405,9 @@ void run_graphs_release()
     for (auto& kv : g_rg) {
         drop_run_graph(kv.second);
         if (kv.second.cap) (void)hipStreamDestroy(kv.second.cap);
+        if (kv.second.done) (void)hipEventDestroy(kv.second.done);
         kv.second.cap = nullptr;
+        kv.second.done = nullptr;
     }
 }
 }  // namespace sd
@@ -563,6 +569,8 @@ sd_status sd_run(const sd_params* p, int64_t n, double* x, const void* force, do
         RunGraph& g = g_rg[dev];
         if (!g.cap && hipStreamCreateWithFlags(&g.cap, hipStreamNonBlocking) != hipSuccess)
             return fail(SD_EDEVICE, "capture stream creation failed");
+        if (!g.done && hipEventCreateWithFlags(&g.done, hipEventDisableTiming) != hipSuccess)
+            return fail(SD_EDEVICE, "event creation failed");
         if (!g.exec || !(g.key == key)) {
             drop_run_graph(g);
             if (hipStreamBeginCapture(g.cap, hipStreamCaptureModeThreadLocal) != hipSuccess)
@@ -589,6 +597,7 @@ sd_status sd_run(const sd_params* p, int64_t n, double* x, const void* force, do
         for (; done + RUN_CHUNK <= steps; done += RUN_CHUNK)
             if (hipGraphLaunch(g.exec, hs) != hipSuccess)
                 return fail(SD_EDEVICE, "hipGraphLaunch failed");
+        if (hipEventRecord(g.done, hs) != hipSuccess) return fail(SD_EDEVICE, "event record failed");
     }
     for (int64_t s = done; s < steps; ++s) {
         if ((st = step_impl(p, n, x, force, vp, nullptr, dt, step0 + s, integrator, precision, stage,

@@ -178,3 +178,29 @@ def test_graph_replays_match_eager(sd, prec, integ, steps, step0):
                 assert torch.isfinite(scratch)
         finally:
             sd.sd_set_graph_mode(1)
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_graph_rebuild_without_sync(sd, prec):
+    """Calls on one stream that alternate between two state buffers rebuild the
+    captured graph on every call while the previous replay may still run; the
+    results are bitwise the eager loop's."""
+    import torch
+    n, steps = 4000, 48
+    x0 = W.random_suspension(n, phi=0.05, seed=43)
+    f = W.gravity_forces(n) + 0.2 * W.gaussian_forces(n, seed=44)
+    frc = to_dev4(f, torch.float64 if prec == 1 else torch.float32)
+    sd.sd_set_graph_mode(0)
+    xe = to_dev3(x0)
+    sd.sd_run(xe, frc, 0.01, 2 * steps, precision=prec)
+    sd.sd_set_graph_mode(2)
+    try:
+        xa, xb = to_dev3(x0), to_dev3(x0)
+        torch.cuda.synchronize()
+        for _ in range(2):
+            sd.sd_run(xa, frc, 0.01, steps, precision=prec)
+            sd.sd_run(xb, frc, 0.01, steps, precision=prec)
+        torch.cuda.synchronize()
+        assert torch.equal(xa, xe) and torch.equal(xb, xe)
+    finally:
+        sd.sd_set_graph_mode(1)
