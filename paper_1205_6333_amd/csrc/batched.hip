@@ -27,14 +27,15 @@ namespace sd {
 
 
 // LDS layout of one work-group (every segment 32-byte aligned):
-//   xs  f64[3M]   FP64 positions of the cluster
+//   xs  2 x f64[3M]   FP64 positions of the cluster, double-buffered: a step
+//                     reads one copy and writes the next positions to the other
 //   fs  f32x4[M] or f64x4[M]   forces
-//   pf  f32x4[M]  FP32 staged positions (FP32 precisions)
+//   pf  2 x f32x4[M]  FP32 staged positions (FP32 precisions), double-buffered
 //   vp  f64[3M]   previous velocities (AB2)
 //   red f64[3*max(WG, M)] per-lane partial velocities (P > 1) or the
-//                 velocities of the cluster (one lane per particle)
+//                 velocities of the cluster (more particles than lanes)
 struct LdsLayout {
-    size_t fs, pf, vp, red, total;
+    size_t xs1, fs, pf, pf1, vp, red, total;
 };
 
 __host__ __device__ inline size_t lds_round(size_t b) { return (b + 31) & ~(size_t)31; }
@@ -45,9 +46,13 @@ __host__ __device__ inline LdsLayout lds_layout(int max_size, int precision, int
     const size_t M = (size_t)max_size;
     LdsLayout L;
     size_t o = lds_round(M * 3 * sizeof(double));
+    L.xs1 = o;
+    o += lds_round(M * 3 * sizeof(double));
     L.fs = o;
     o += lds_round(M * (precision == SD_FP64 ? sizeof(double4) : sizeof(float4)));
     L.pf = o;
+    if (precision != SD_FP64) o += lds_round(M * sizeof(float4));
+    L.pf1 = o;
     if (precision != SD_FP64) o += lds_round(M * sizeof(float4));
     L.vp = o;
     if (integrator == SD_AB2) o += lds_round(M * 3 * sizeof(double));
@@ -206,6 +211,10 @@ __device__ __forceinline__ void b_velocity(int i, int sub, int P, int nc, const 
 
 // RUN: `steps` steps per cluster, positions written back to x.
 // APPLY (steps < 0): one product, velocities written to vel.
+// Per step: every lane computes its share of the velocities from one copy of
+// the positions, the owners of the particles write the next positions to the
+// other copy, and one barrier ends the step (two when P > 1: the partial
+// velocities of a particle are summed by its owner after a barrier).
 template <int TENSOR, int PREC, int INTEG, int WG>
 __global__ void __launch_bounds__(WG)
 k_batched(BatchDev b, PairConst pc, double* __restrict__ x, const void* __restrict__ frc,
@@ -214,16 +223,18 @@ k_batched(BatchDev b, PairConst pc, double* __restrict__ x, const void* __restri
     constexpr int BB = WG;
     extern __shared__ __align__(32) unsigned char lds[];
     const LdsLayout lay = lds_layout(b.max_size, PREC, INTEG, WG);
-    double* xs = (double*)lds;
+    double* const xs0 = (double*)lds;
+    double* const xs1 = (double*)(lds + lay.xs1);
     void* fs = lds + lay.fs;
-    float4* pf = (PREC != SD_FP64) ? (float4*)(lds + lay.pf) : nullptr;
+    float4* const pf0 = (PREC != SD_FP64) ? (float4*)(lds + lay.pf) : nullptr;
+    float4* const pf1 = (PREC != SD_FP64) ? (float4*)(lds + lay.pf1) : nullptr;
     double* vp = (INTEG == SD_AB2) ? (double*)(lds + lay.vp) : nullptr;
     double* red = (double*)(lds + lay.red);
     __shared__ int s_item;
     const int t = threadIdx.x;
 
     for (;;) {
-        __syncthreads();
+        __syncthreads();  // the previous cluster's write-back has read every copy
         if (t == 0) s_item = atomicAdd(b.counter, 1);
         __syncthreads();
         const int item = s_item;
@@ -234,25 +245,28 @@ k_batched(BatchDev b, PairConst pc, double* __restrict__ x, const void* __restri
         if (nc <= 0) continue;
         for (int k = t; k < nc; k += BB) {
             const size_t g = (size_t)(off + k);
-            xs[3 * k] = x[3 * g];
-            xs[3 * k + 1] = x[3 * g + 1];
-            xs[3 * k + 2] = x[3 * g + 2];
+            const double x0 = x[3 * g], x1 = x[3 * g + 1], x2 = x[3 * g + 2];
+            xs0[3 * k] = x0;
+            xs0[3 * k + 1] = x1;
+            xs0[3 * k + 2] = x2;
+            if (PREC != SD_FP64) pf0[k] = make_float4((float)x0, (float)x1, (float)x2, 0.0f);
             if (PREC == SD_FP64)
                 ((double4*)fs)[k] = ((const double4*)frc)[g];
             else
                 ((float4*)fs)[k] = ((const float4*)frc)[g];
         }
+        __syncthreads();
         const int P = nc <= BB ? BB / nc : 1;
         const int rows = nc <= BB ? 1 : (nc + BB - 1) / BB;
         const int nsteps = steps < 0 ? 1 : steps;
+        // current copy (read this step) and next copy (written this step)
+        double* xs = xs0;
+        double* xn = xs1;
+        float4* pf = pf0;
+        float4* pn = pf1;
         for (int st = 0; st < nsteps; ++st) {
-            __syncthreads();
-            if (PREC != SD_FP64)
-                for (int k = t; k < nc; k += BB)
-                    pf[k] = make_float4((float)xs[3 * k], (float)xs[3 * k + 1],
-                                        (float)xs[3 * k + 2], 0.0f);
-            __syncthreads();
-            double v[3] = { 0.0, 0.0, 0.0 };  // P > 1: the owner's velocity
+            // velocities (pair part) of the particles this lane owns
+            double v[3] = { 0.0, 0.0, 0.0 };  // rows == 1: the owner's velocity
             if (P > 1) {
                 const int i = t / P, sub = t % P;
                 double w[3] = { 0.0, 0.0, 0.0 };
@@ -267,8 +281,10 @@ k_batched(BatchDev b, PairConst pc, double* __restrict__ x, const void* __restri
                         v[1] += red[3 * (t + u) + 1];
                         v[2] += red[3 * (t + u) + 2];
                     }
+            } else if (rows == 1) {
+                if (t < nc) b_velocity<TENSOR, PREC>(t, 0, 1, nc, xs, fs, pf, pc, v);
             } else {
-                // one lane per particle, rows of BB particles; velocities to LDS
+                // rows of BB particles per lane: velocities to this lane's slots
                 for (int r = 0; r < rows; ++r) {
                     const int i = t + r * BB;
                     if (i >= nc) break;
@@ -279,15 +295,14 @@ k_batched(BatchDev b, PairConst pc, double* __restrict__ x, const void* __restri
                     red[3 * i + 2] = w[2];
                 }
             }
-            __syncthreads();  // every read of xs / pf / red of this step is done
-            const int nrow = P > 1 ? 1 : rows;
-            for (int r = 0; r < nrow; ++r) {
+            // owners: velocity out (APPLY) or the next positions into the other copy
+            for (int r = 0; r < rows; ++r) {
                 const int i = (P > 1) ? t / P : t + r * BB;
                 const bool own = (P > 1) ? (t % P == 0 && i < nc) : (i < nc);
                 if (!own) continue;
-                const double w0 = P > 1 ? v[0] : red[3 * i];
-                const double w1 = P > 1 ? v[1] : red[3 * i + 1];
-                const double w2 = P > 1 ? v[2] : red[3 * i + 2];
+                const double w0 = rows == 1 ? v[0] : red[3 * i];
+                const double w1 = rows == 1 ? v[1] : red[3 * i + 1];
+                const double w2 = rows == 1 ? v[2] : red[3 * i + 2];
                 double f0, f1, f2;
                 if (PREC == SD_FP64) {
                     const double4 f = ((const double4*)fs)[i];
@@ -304,18 +319,28 @@ k_batched(BatchDev b, PairConst pc, double* __restrict__ x, const void* __restri
                     vel[3 * g + 2] = vv[2];
                     continue;
                 }
+                double xnew[3];
                 for (int k = 0; k < 3; ++k) {
                     double inc = vv[k];
                     if (INTEG == SD_AB2) {
                         if (st > 0) inc = 1.5 * vv[k] - 0.5 * vp[3 * i + k];
                         vp[3 * i + k] = vv[k];
                     }
-                    xs[3 * i + k] += dt * inc;
+                    xnew[k] = xs[3 * i + k] + dt * inc;
+                    xn[3 * i + k] = xnew[k];
                 }
+                if (PREC != SD_FP64)
+                    pn[i] = make_float4((float)xnew[0], (float)xnew[1], (float)xnew[2], 0.0f);
             }
+            __syncthreads();  // the next step reads the copy written above
+            double* const tx = xs;
+            xs = xn;
+            xn = tx;
+            float4* const tp = pf;
+            pf = pn;
+            pn = tp;
         }
         if (steps >= 0) {
-            __syncthreads();
             for (int k = t; k < nc; k += BB) {
                 const size_t g = (size_t)(off + k);
                 x[3 * g] = xs[3 * k];
