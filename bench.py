@@ -142,11 +142,25 @@ def cpu_baseline(x32, f32, vgpu, n, target_s):
         ref = oracle.mobility_rows(p, x32, f32, rows)
         dt = time.perf_counter() - t0
     err = float(np.linalg.norm(vgpu[rows] - ref) / np.linalg.norm(ref))
+    cores = oracle.threads()
+    # the same loop on one thread, over a smaller sample (about 2 s)
+    rows1 = np.sort(rng.choice(n, size=max(16, min(n, int(len(rows) * 2.0 / max(dt, 1e-3)
+                                                          / max(cores, 1)))), replace=False))
+    oracle.set_threads(1)
+    try:
+        t0 = time.perf_counter()
+        oracle.mobility_rows(p, x32, f32, rows1)
+        dt1 = time.perf_counter() - t0
+    finally:
+        oracle.set_threads(cores)
     return {"value": len(rows) * n / dt / 1e9, "unit": "G pair-interactions/s",
-            "cores": oracle.threads(), "kind": "oracle",
+            "cores": cores, "kind": "oracle",
             "sample": "%d of %d rows of the N=%d product (%.2e pairs, %.1f s), FP64 oracle "
                       "(plain double loop, gcc -O2, OpenMP over rows)" % (len(rows), n, n,
-                                                                          len(rows) * n, dt)}, err
+                                                                          len(rows) * n, dt),
+            "single_thread_value": len(rows1) * n / dt1 / 1e9,
+            "single_thread_sample": "%d rows (%.2e pairs, %.1f s) on one thread"
+                                    % (len(rows1), len(rows1) * n, dt1)}, err
 
 
 def _sync_time(fn):

@@ -70,6 +70,8 @@ def _load():
         lib.oracle_run_adjoint_euler.restype = ctypes.c_int
         lib.oracle_threads.argtypes = []
         lib.oracle_threads.restype = ctypes.c_int
+        lib.oracle_set_threads.argtypes = [ctypes.c_int]
+        lib.oracle_set_threads.restype = None
         LP = ctypes.POINTER(OracleLub)
         lib.oracle_lub_tensor.argtypes = [P, LP, d, d]
         lib.oracle_lubrication_force.argtypes = [P, LP, i64, d, d, d]
@@ -83,6 +85,11 @@ def _load():
 def threads() -> int:
     """Threads the oracle's parallel loops use."""
     return int(_load().oracle_threads())
+
+
+def set_threads(k: int) -> None:
+    """Run the oracle's parallel loops on k threads (for timing)."""
+    _load().oracle_set_threads(int(k))
 
 
 def params(a: float = 1.0, eta: float = 1.0 / (6.0 * np.pi), tensor: int = RPY,

@@ -61,6 +61,16 @@ int oracle_threads(void)
 #endif
 }
 
+/* Set the number of threads of the parallel loops (no effect without OpenMP). */
+void oracle_set_threads(int k)
+{
+#ifdef _OPENMP
+    if (k > 0) omp_set_num_threads(k);
+#else
+    (void)k;
+#endif
+}
+
 /* Nearest image (footnote of Sec. 3.1): in a periodic box only the nearest
  * image of each particle interacts.  r = r_i - r_j is replaced by the
  * periodic copy of least length along every periodic axis (ties at exactly
