@@ -539,7 +539,7 @@ def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
-    ap.add_argument("--warmup", type=int, default=10,
+    ap.add_argument("--warmup", type=int, default=100,
                     help="untimed products first (the clock ramps up over the first launches)")
     ap.add_argument("--n", type=int, default=65536)
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
