@@ -186,3 +186,25 @@ def test_parity_sampled_65536(sd, orc):
     v64 = _run(sd, x, f, 1, ps)
     ref64 = orc.mobility_rows(po, x, f, rows)
     assert rel2(v64[rows], ref64) <= TOL[1]
+
+
+def test_parity_sampled_2_20(sd, orc):
+    """n = 2^20 (a jittered fcc lattice at 0.1 / a^3, nearest pairs 2.3a apart),
+    in the automatic launch configuration: sampled rows against the oracle in
+    free space and in the periodic cube of the lattice, FP32 + Kahan and FP64."""
+    n = 1 << 20
+    x, L = W.jittered_fcc(64)
+    assert x.shape[0] == n
+    f = W.gaussian_forces(n, seed=7)
+    rows = np.unique(np.concatenate([[0, n - 1],
+                                     np.random.default_rng(8).choice(n, 254, replace=False)]))
+    xo, fo = W.round_to_f32(x), W.round_to_f32(f)
+    for box in (None, L):
+        ps = sd.params(box=box) if box else sd.params()
+        po = orc.params(box=box) if box else orc.params()
+        v = _run(sd, x, f, 0, ps)
+        err = rel2(v[rows], orc.mobility_rows(po, xo, fo, rows))
+        v64 = _run(sd, x, f, 1, ps)
+        err64 = rel2(v64[rows], orc.mobility_rows(po, x, f, rows))
+        print("n=2^20 box=%s fp32-kahan rel2=%.3e fp64 rel2=%.3e" % (box, err, err64))
+        assert err <= TOL[0] and err64 <= TOL[1]
