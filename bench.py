@@ -85,14 +85,21 @@ def _measured_traffic(n, cfg):
 # VALU wave instructions of one product-kernel launch (rocprofv3 SQ_INSTS_VALU,
 # profiles/pair_kernel_f32_n65536_valu_counters.md), same validity rule.
 PMC_VALU = {"source_sha1": PMC_TRAFFIC["source_sha1"], "n": 65536,
-            "config": PMC_TRAFFIC["config"], "valu_wave_instr": 1634484224}
+            "config": PMC_TRAFFIC["config"], "valu_wave_instr": 1634484224,
+            # SQ_INSTS_VALU_{ADD,MUL,FMA,TRANS}_F32 per dispatch (wave instructions)
+            "add_f32": 276824064, "mul_f32": 402685952, "fma_f32": 805306368,
+            "trans_f32": 67141632}
 
 
 def _measured_valu(n, cfg):
-    """VALU lane-instructions per launch, or None if the counters are stale."""
+    """(VALU lane-instructions, issued FP32 flops) per launch, or None if the
+    counters are stale.  Issued flops: add, mul and transcendental count one,
+    FMA two, per lane."""
     if _measured_traffic(n, cfg) is None or PMC_VALU["n"] != n or dict(cfg) != PMC_VALU["config"]:
         return None
-    return 64.0 * PMC_VALU["valu_wave_instr"]
+    v = PMC_VALU
+    flops = 64.0 * (v["add_f32"] + v["mul_f32"] + 2 * v["fma_f32"] + v["trans_f32"])
+    return 64.0 * v["valu_wave_instr"], flops
 
 
 def _to4(v, dtype, device):
@@ -612,8 +619,11 @@ def main():
                        "kernel": "pair kernel (k_pair_f32_*)"}
     valu = _measured_valu(n, cfg)
     if valu is not None:
-        out["roofline"]["valu_lane_instr_per_pair"] = valu / pairs
-        out["roofline"]["valu_t_lane_instr_per_s"] = valu / (kern_ms * 1e-3) / 1e12
+        instr, flops = valu
+        out["roofline"]["valu_lane_instr_per_pair"] = instr / pairs
+        out["roofline"]["valu_t_lane_instr_per_s"] = instr / (kern_ms * 1e-3) / 1e12
+        out["roofline"]["issued_flop_per_pair"] = flops / pairs
+        out["roofline"]["issued_tflops"] = flops / (kern_ms * 1e-3) / 1e12
     if not args.no_fp64:
         pos64, frc64 = _to4(x, torch.float64, dev), _to4(f, torch.float64, dev)
         vel64 = torch.empty((n, 3), dtype=torch.float64, device=dev)
