@@ -18,6 +18,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 #include <numeric>
 #include <cstdio>
 #include <string>
@@ -483,7 +484,8 @@ struct sd_batch {
 
 namespace sd {
 
-static std::vector<sd_batch*> g_batches;
+static std::vector<sd_batch*> g_batches;  // live plans (for sd_release)
+static std::mutex g_batches_mu;
 
 // Waits for the last replay before the executable graph is destroyed.
 static void drop_graph(sd_batch* b)
@@ -498,6 +500,7 @@ static void drop_graph(sd_batch* b)
 
 void batch_release_graphs()
 {
+    std::lock_guard<std::mutex> lk(g_batches_mu);
     for (sd_batch* b : g_batches) drop_graph(b);
 }
 
@@ -600,7 +603,10 @@ sd_status sd_batch_create(const sd_params* p, int64_t n_clusters, const int64_t*
         delete b;
         return fail(SD_EDEVICE, "plan upload failed");
     }
-    g_batches.push_back(b);
+    {
+        std::lock_guard<std::mutex> lk(g_batches_mu);
+        g_batches.push_back(b);
+    }
     *out = b;
     return SD_OK;
 }
@@ -608,12 +614,15 @@ sd_status sd_batch_create(const sd_params* p, int64_t n_clusters, const int64_t*
 sd_status sd_batch_destroy(sd_batch* b)
 {
     if (!b) return SD_OK;
+    {   // off the list first, so that sd_release no longer reaches it
+        std::lock_guard<std::mutex> lk(g_batches_mu);
+        g_batches.erase(std::remove(g_batches.begin(), g_batches.end(), b), g_batches.end());
+    }
     (void)hipDeviceSynchronize();
     drop_graph(b);
     if (b->cap) (void)hipStreamDestroy(b->cap);
     if (b->done) (void)hipEventDestroy(b->done);
     if (b->dmem) (void)hipFree(b->dmem);
-    g_batches.erase(std::remove(g_batches.begin(), g_batches.end(), b), g_batches.end());
     delete b;
     return SD_OK;
 }

@@ -7,6 +7,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -270,7 +271,7 @@ sd_status check_config(int32_t prec, const sd_kernel_config& c)
 // ---------------------------------------------------------------- profiling
 
 struct Profile {
-    bool on = false;
+    std::atomic<bool> on{ false };   // read without the lock on every launch
     std::vector<std::pair<hipEvent_t, hipEvent_t>> pending;
     int64_t launches = 0;
     double total_ms = 0.0;
@@ -381,7 +382,7 @@ struct RunGraph {
 
 std::mutex g_rg_mu;
 std::map<int, RunGraph> g_rg;
-int32_t g_graph_mode = 1;   // 0 off, 1 automatic (n <= RUN_GRAPH_AUTO_N), 2 always
+std::atomic<int32_t> g_graph_mode{ 1 };   // 0 off, 1 automatic (n <= RUN_GRAPH_AUTO_N), 2 always
 constexpr int64_t RUN_GRAPH_AUTO_N = 16384;
 
 // Waits for the last replay before the executable graph is destroyed (a
@@ -539,8 +540,9 @@ sd_status sd_run(const sd_params* p, int64_t n, double* x, const void* force, do
         return st;
     double* vp = integrator == SD_AB2 ? v_prev : nullptr;
     int64_t done = 0;
+    const int32_t gmode = g_graph_mode.load();
     const bool graphed = !x_checkpoints && !g_prof.on && steps >= 2 * RUN_CHUNK &&
-                         (g_graph_mode == 2 || (g_graph_mode == 1 && n <= RUN_GRAPH_AUTO_N));
+                         (gmode == 2 || (gmode == 1 && n <= RUN_GRAPH_AUTO_N));
     if (graphed) {
         // the first AB2 step (an Euler step that stores v_prev) stays eager
         if (integrator == SD_AB2 && step0 == 0) {
