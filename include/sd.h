@@ -383,8 +383,14 @@ sd_status sd_membench(int32_t kind, int32_t map, int32_t elem, int64_t n, const 
 /* Kernel shape of the all-pairs product. */
 typedef struct sd_kernel_config {
     int32_t variant;      /* 0 = j-tiles staged in LDS, 1 = j data through the
-                             scalar cache */
-    int32_t block;        /* work-group size (64, 128 or 256) */
+                             scalar cache, 2 = pair symmetry (FP32 precisions
+                             only): every pair of particles in different
+                             blocks evaluated once, T(r_ij) F_i handed to j
+                             (block symmetry of M, Sec. 3.3); ilp 1,
+                             kahan_block 0, 4 or 8; library workspace of
+                             about 6 n^2 / block bytes */
+    int32_t block;        /* work-group size (64, 128 or 256; variant 2: 128,
+                             256 or 512) */
     int32_t splits;       /* j-range splits (>= 1): extra work-groups per i-block */
     int32_t ilp;          /* particles i per lane (1 or 2) */
     int32_t kahan_block;  /* SD_FP32_KAHAN: pair terms summed in FP32 before each

@@ -17,6 +17,7 @@
 #include "sd_internal.h"
 
 #include <cmath>
+#include <type_traits>
 
 namespace sd {
 
@@ -49,6 +50,13 @@ PairLaunch shape_pair_launch(int n, int variant, int block, int splits, int ilp)
     L.variant = variant;
     L.block = block;
     L.ilp = ilp;
+    if (variant == 2) {
+        // rows: the symmetric splits, the diagonal blocks, the folded j side
+        const SymShape sh = sym_shape(n, block, splits);
+        L.jchunk = sh.chunk;
+        L.splits = sh.isplits + 2;
+        return L;
+    }
     if (splits < 1) splits = 1;
     // j chunks are whole tiles of `block` particles
     const int tiles = (n + block - 1) / block;
@@ -453,6 +461,418 @@ k_pair_f32_smem(const float4* __restrict__ pos, const float4* __restrict__ frc,
     lanes_store<ILP>(L, n, s, pc.alpha_sum, near_slot, NS, partial);
 }
 
+// ------------------------------------------------ variant 2: pair symmetry
+//
+// The blocks of M satisfy M_ji = M_ij^T and T is even in r (Sec. 3.3 uses
+// mu_ij = mu_ji on the CPU), so one evaluation of the coefficients A', Bt' of
+// a pair gives both T(r_ij) F_j for i and T(r_ij) F_i for j.  Variant 2
+// evaluates every pair of particles in different blocks once:
+//
+// Block schedule.  Particles are cut into nb blocks of BLOCK.  Work-group
+// (I, s) owns i-block I.  The blocks J = I + 1 .. I + h (mod nb), h =
+// (nb - 1) / 2, and, when nb is even, J = I + nb/2 for I < nb/2 only, form a
+// virtual j range p = (J - I - 1 mod nb) BLOCK + offset, cut into splits of
+// `chunk` positions.  Every unordered pair of distinct blocks is thus taken
+// exactly once.  The diagonal blocks J = I are taken one-sided (every ordered
+// pair, as variant 0) by nb extra work-groups dispatched last.
+//
+// Rows of 16 lanes.  Each 16-lane row of a wave holds 16 particles i, one
+// per lane.  A tile of SYM_TJ particles j is staged in LDS in chunks of 16,
+// each chunk stored twice in a row, so that lane q reads element (q + k) mod
+// 16 of a chunk at the constant offset k.  In step k of a chunk lane q pairs
+// its i with that element; the j-side term goes to the lane that owns the
+// element through a DPP row rotation (row_ror:k: lane m reads lane m - k),
+// so every lane accumulates the j-side sum of one element of the chunk and
+// no cross-lane reduction is needed.  After a chunk each row stores its 16
+// j-side sums in LDS; at the end of a tile the rows are added in a fixed
+// order and written as FP32 j-side partials jpart[c][I][p] (scaled units),
+// which k_fold_sym adds in FP64, in a fixed order, into one more split row.
+
+constexpr int SYM_TJ = 128;   // j tile: 8 chunks of 16
+
+SymShape sym_shape(int n, int block, int splits)
+{
+    SymShape sh;
+    sh.nb = (n + block - 1) / block;
+    sh.h = (sh.nb - 1) / 2;
+    sh.extra = (sh.nb >= 2 && (sh.nb & 1) == 0) ? 1 : 0;
+    sh.lmax = (sh.h + sh.extra) * block;
+    int s = splits < 1 ? 1 : splits;
+    const int tiles = sh.lmax / SYM_TJ;
+    if (s > tiles) s = tiles > 0 ? tiles : 1;
+    const int per = (tiles + s - 1) / s;
+    sh.chunk = (per > 0 ? per : 1) * SYM_TJ;
+    sh.isplits = sh.lmax > 0 ? (sh.lmax + sh.chunk - 1) / sh.chunk : 1;
+    return sh;
+}
+
+SymShape sym_shape_of(const PairLaunch& L, int n)
+{
+    SymShape sh = sym_shape(n, L.block, 1);
+    sh.chunk = L.jchunk;
+    sh.isplits = L.splits - 2;
+    return sh;
+}
+
+size_t sym_jpart_floats(const SymShape& sh) { return (size_t)3 * sh.nb * (size_t)sh.lmax; }
+
+size_t sym_jpart_offset(const PairLaunch& L, int64_t n)
+{
+    const size_t b = (size_t)L.splits * 3 * (size_t)n * sizeof(double);
+    return (b + 255) & ~(size_t)255;
+}
+
+// Compile-time loop: f(integral_constant<int, U>) for U = B .. E-1.
+template <int B, int E>
+struct StaticFor {
+    template <class F>
+    __device__ __forceinline__ static void run(F&& f)
+    {
+        f(std::integral_constant<int, B>());
+        StaticFor<B + 1, E>::run(f);
+    }
+};
+template <int E>
+struct StaticFor<E, E> {
+    template <class F>
+    __device__ __forceinline__ static void run(F&&) {}
+};
+
+// acc + (value v of lane (lane - K) mod 16 of the same row)
+template <int K>
+__device__ __forceinline__ float add_row_rot(float acc, float v)
+{
+    if constexpr (K == 0) {
+        return acc + v;
+    } else {
+        return acc + __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(
+                                                  0, __builtin_bit_cast(int, v), 0x120 + K, 0xf,
+                                                  0xf, true));
+    }
+}
+
+// One near pair (i, j) of the symmetric kernel in FP64: T(r_ij) F_j is added
+// to the lane's LDS slot, T(r_ij) F_i (= T(r_ji) F_i) is returned in v*.
+// Out of line: the rare branch then holds no registers of the hot loop.
+template <int TENSOR, bool PER, int BLOCK>
+__device__ __attribute__((noinline)) void sym_near_pair(const LaneF32& L, float fi0, float fi1,
+                                                       float fi2, float4 pj, float4 fj, int jg,
+                                                       const PairConst& pc,
+                                                       const double* __restrict__ x64,
+                                                       double* near_slot, double& v0, double& v1,
+                                                       double& v2)
+{
+    double d0, d1, d2;
+    near_diff<PER>(L, pj, jg, pc, x64, d0, d1, d2);
+    double n0 = near_slot[0], n1 = near_slot[BLOCK], n2 = near_slot[2 * BLOCK];
+    near_term<TENSOR>(pc, d0, d1, d2, (double)fj.x, (double)fj.y, (double)fj.z, n0, n1, n2);
+    near_slot[0] = n0;
+    near_slot[BLOCK] = n1;
+    near_slot[2 * BLOCK] = n2;
+    near_term<TENSOR>(pc, d0, d1, d2, (double)fi0, (double)fi1, (double)fi2, v0, v1, v2);
+}
+
+// Steps K0 .. K0+7 of a chunk for one lane: pairs (i, element (q + k) mod 16).
+// sp/sf: this lane's view of the doubled chunk (element (q + k) mod 16 at
+// offset k).  jgc: global index of element 0 of the chunk.  aj*: the j-side
+// sums of element q (scaled units), started by step 0.
+template <int TENSOR, int ACC, bool PER, int K0, int BLOCK>
+__device__ __forceinline__ void sym_steps(LaneF32& L, float fi0, float fi1, float fi2, float& aj0,
+                                          float& aj1, float& aj2, const float4* sp,
+                                          const float4* sf, int jgc, int q, int n,
+                                          const PairConst& pc, float gamma, float m3g,
+                                          float thr2, double inv_alpha_sum,
+                                          const double* __restrict__ x64, double* near_slot)
+{
+    constexpr int U = 8;
+    // groups of eight steps are scheduled one after the other: overlapping
+    // them would hold two groups of pair data in registers
+    __builtin_amdgcn_sched_barrier(0);
+    float4 pj[U], fj[U];
+    float dx[U], dy[U], dz[U], r2[U];
+    float rmin = 3.0e38f;
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        pj[u] = sp[K0 + u];
+        fj[u] = sf[K0 + u];
+        dx[u] = pdiff<PER>(L.x, pj[u].x);
+        dy[u] = pdiff<PER>(L.y, pj[u].y);
+        dz[u] = pdiff<PER>(L.z, pj[u].z);
+        r2[u] = fmaf(dx[u], dx[u], fmaf(dy[u], dy[u], dz[u] * dz[u]));
+        rmin = fminf(rmin, r2[u]);
+    }
+    // near pairs (rare): masked out of the FP32 code here, evaluated in FP64
+    // after it, when this group's FP32 data are no longer live
+    uint32_t nmask = 0;
+    if (__builtin_amdgcn_ballot_w64(rmin < thr2) != 0) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const bool nr = r2[u] < thr2;
+            nmask |= nr ? (1u << u) : 0u;
+            r2[u] = nr ? __builtin_inff() : r2[u];
+        }
+    }
+    constexpr int KB = ACC > 0 ? ACC : 1;
+    StaticFor<0, U / KB>::run([&](auto b_c) {
+        constexpr int u0 = decltype(b_c)::value * KB;
+        float y0 = ACC ? -L.c0 : L.s0;
+        float y1 = ACC ? -L.c1 : L.s1;
+        float y2 = ACC ? -L.c2 : L.s2;
+        StaticFor<u0, u0 + KB>::run([&](auto u_c) {
+            constexpr int u = decltype(u_c)::value;
+            const float rinv = __builtin_amdgcn_rsqf(r2[u]);
+            const float rinv2 = rinv * rinv;
+            const float rinv3 = rinv2 * rinv;
+            float A, Bt;
+            if (TENSOR == T_OSEEN) {
+                A = rinv;
+                Bt = rinv3;
+            } else {
+                A = fmaf(gamma, rinv3, rinv);
+                Bt = rinv3 * fmaf(m3g, rinv2, 1.0f);
+            }
+            // i side: T F_j
+            const float dFj = fmaf(dx[u], fj[u].x, fmaf(dy[u], fj[u].y, dz[u] * fj[u].z));
+            const float sBj = Bt * dFj;
+            y0 = fmaf(A, fj[u].x, fmaf(sBj, dx[u], y0));
+            y1 = fmaf(A, fj[u].y, fmaf(sBj, dy[u], y1));
+            y2 = fmaf(A, fj[u].z, fmaf(sBj, dz[u], y2));
+            // j side: T F_i, handed to the lane that owns the element
+            const float dFi = fmaf(dx[u], fi0, fmaf(dy[u], fi1, dz[u] * fi2));
+            const float sBi = Bt * dFi;
+            const float c0 = fmaf(A, fi0, sBi * dx[u]);
+            const float c1 = fmaf(A, fi1, sBi * dy[u]);
+            const float c2 = fmaf(A, fi2, sBi * dz[u]);
+            if constexpr (K0 + u == 0) {  // first step of a chunk starts the sums
+                aj0 = c0;
+                aj1 = c1;
+                aj2 = c2;
+            } else {
+                aj0 = add_row_rot<(K0 + u) & 15>(aj0, c0);
+                aj1 = add_row_rot<(K0 + u) & 15>(aj1, c1);
+                aj2 = add_row_rot<(K0 + u) & 15>(aj2, c2);
+            }
+        });
+        if (ACC) {
+            const float t0 = L.s0 + y0;
+            const float t1 = L.s1 + y1;
+            const float t2 = L.s2 + y2;
+            L.c0 = (t0 - L.s0) - y0;
+            L.c1 = (t1 - L.s1) - y1;
+            L.c2 = (t2 - L.s2) - y2;
+            L.s0 = t0;
+            L.s1 = t1;
+            L.s2 = t2;
+        } else {
+            L.s0 = y0;
+            L.s1 = y1;
+            L.s2 = y2;
+        }
+    });
+    if (__builtin_amdgcn_ballot_w64(nmask != 0) != 0) {
+        // The lane index and the tile pointers pass through an empty asm:
+        // the index arithmetic of this branch is not hoisted into the hot
+        // loop, and the tile is read again here instead of keeping the
+        // group's records live across the FP32 code.
+        int qn = q;
+        const float4* spn = sp;
+        const float4* sfn = sf;
+        asm volatile("" : "+v"(qn), "+v"(spn), "+v"(sfn));
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const bool nr = (nmask >> u) & 1u;
+            if (__builtin_amdgcn_ballot_w64(nr) == 0) continue;
+            const int jg = jgc + ((qn + K0 + u) & 15);
+            double v0 = 0.0, v1 = 0.0, v2 = 0.0;
+            if (nr && L.i < n && jg < n && jg != L.i)
+                sym_near_pair<TENSOR, PER, BLOCK>(L, fi0, fi1, fi2, spn[K0 + u], sfn[K0 + u], jg,
+                                                  pc, x64, near_slot, v0, v1, v2);
+            // the owner of element (q + k) mod 16 is lane q + k of the row
+            const int lane = (int)(threadIdx.x & 63);
+            const int src = (lane & ~15) | ((qn - (K0 + u)) & 15);
+            v0 = __shfl(v0, src);
+            v1 = __shfl(v1, src);
+            v2 = __shfl(v2, src);
+            aj0 += (float)(v0 * inv_alpha_sum);
+            aj1 += (float)(v1 * inv_alpha_sum);
+            aj2 += (float)(v2 * inv_alpha_sum);
+            // one near step at a time: keeps the FP64 temporaries of different
+            // steps from being live together
+            __builtin_amdgcn_sched_barrier(0);
+        }
+    }
+}
+
+template <int TENSOR, int ACC, int BLOCK, bool PER>
+__global__ void __launch_bounds__(BLOCK)
+k_pair_f32_sym(const float4* __restrict__ pos, const float4* __restrict__ frc,
+               const double* __restrict__ x64, int n, SymShape sh, PairConst pc,
+               double* __restrict__ partial, float* __restrict__ jpart)
+{
+    static_assert(BLOCK % SYM_TJ == 0, "j tiles must not straddle blocks");
+    constexpr int ROWS = BLOCK / 16;
+    constexpr int NPOS = BLOCK > 2 * SYM_TJ ? BLOCK : 2 * SYM_TJ;
+    __shared__ float4 s_pos[NPOS];
+    __shared__ float4 s_frc[NPOS];
+    __shared__ double s_near[3 * BLOCK];
+    __shared__ float s_jacc[3 * ROWS * SYM_TJ];
+    const int tid = threadIdx.x;
+    const int nsym = sh.nb * sh.isplits;
+    const bool diag = (int)blockIdx.x >= nsym;
+    int ib, s;
+    if (diag) {
+        ib = (int)blockIdx.x - nsym;
+        s = sh.isplits;
+    } else {
+        map_block(sh.isplits, ib, s);
+    }
+    LaneF32 L[1];
+    lanes_init<1, BLOCK, PER>(L, pos, n, ib);
+    double* near_slot = near_slots_init<1, BLOCK>(s_near);
+    const float gamma = pc.gamma_f, m3g = pc.m3gamma_f, thr2 = pc.thr2_f;
+    const float4 far_j4 = make_float4(far_j<PER>(), far_j<PER>(), far_j<PER>(), 0.0f);
+    const float4 zero4 = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+
+    if (diag) {
+        // the i-block with itself: every ordered pair, one-sided, in groups of
+        // four (compensation at least every four terms; groups of eight here
+        // would raise the register count of the whole kernel)
+        constexpr int ACC_D = ACC > 4 ? 4 : ACC;
+        constexpr int GROUP_U = GroupSize<ACC_D>::value;
+        const int jt = ib * BLOCK;
+        float4 rp = far_j4, rf = zero4;
+        if (jt + tid < n) {
+            rp = pos[jt + tid];
+            rf = frc[jt + tid];
+        }
+        s_pos[tid] = rp;
+        s_frc[tid] = rf;
+        __syncthreads();
+#pragma unroll 1
+        for (int k = 0; k < BLOCK; k += GROUP_U) {
+            float4 pj[GROUP_U], fj[GROUP_U];
+#pragma unroll
+            for (int u = 0; u < GROUP_U; ++u) {
+                pj[u] = s_pos[k + u];
+                fj[u] = s_frc[k + u];
+            }
+            pair_group<TENSOR, ACC_D, GROUP_U, 1, PER>(L, pj, fj, jt + k, n, pc, gamma, m3g,
+                                                       thr2, x64, near_slot, BLOCK);
+        }
+        lanes_store<1>(L, n, s, pc.alpha_sum, near_slot, BLOCK, partial);
+        return;
+    }
+
+    float fi0 = 0.0f, fi1 = 0.0f, fi2 = 0.0f;
+    if (L[0].i < n) {
+        const float4 f = frc[L[0].i];
+        fi0 = f.x;
+        fi1 = f.y;
+        fi2 = f.z;
+    }
+    const double inv_alpha_sum = 1.0 / pc.alpha_sum;
+    const int q = tid & 15;
+    const int row = tid >> 4;
+    const int half = sh.nb >> 1;
+    const int lI = (sh.h + ((sh.extra && ib < half) ? 1 : 0)) * BLOCK;
+    const int pbeg = s * sh.chunk;
+    const int pend = min(lI, pbeg + sh.chunk);
+    // tile element tid (threads tid < SYM_TJ) of the tile at virtual position pt
+    auto tile_first = [&](int pt) {
+        const int J = (ib + 1 + pt / BLOCK) % sh.nb;
+        return J * BLOCK + (pt % BLOCK);
+    };
+    float4 rp = far_j4, rf = zero4;
+    if (pbeg < pend && tid < SYM_TJ) {
+        const int j = tile_first(pbeg) + tid;
+        if (j < n) {
+            rp = pos[j];
+            rf = frc[j];
+        }
+    }
+    for (int pt = pbeg; pt < pend; pt += SYM_TJ) {
+        const int jt = tile_first(pt);
+        __syncthreads();
+        if (tid < SYM_TJ) {
+            const int c = tid >> 4, e = tid & 15;
+            s_pos[c * 32 + e] = rp;
+            s_pos[c * 32 + 16 + e] = rp;
+            s_frc[c * 32 + e] = rf;
+            s_frc[c * 32 + 16 + e] = rf;
+        }
+        __syncthreads();
+        rp = far_j4;
+        rf = zero4;
+        if (pt + SYM_TJ < pend && tid < SYM_TJ) {
+            const int j = tile_first(pt + SYM_TJ) + tid;
+            if (j < n) {
+                rp = pos[j];
+                rf = frc[j];
+            }
+        }
+#pragma unroll 1
+        for (int c = 0; c < SYM_TJ / 16; ++c) {
+            float aj0, aj1, aj2;
+            const float4* sp = s_pos + c * 32 + q;
+            const float4* sf = s_frc + c * 32 + q;
+            const int jgc = jt + c * 16;
+            sym_steps<TENSOR, ACC, PER, 0, BLOCK>(L[0], fi0, fi1, fi2, aj0, aj1, aj2, sp, sf, jgc,
+                                                  q, n, pc, gamma, m3g, thr2, inv_alpha_sum, x64,
+                                                  near_slot);
+            sym_steps<TENSOR, ACC, PER, 8, BLOCK>(L[0], fi0, fi1, fi2, aj0, aj1, aj2, sp, sf, jgc,
+                                                  q, n, pc, gamma, m3g, thr2, inv_alpha_sum, x64,
+                                                  near_slot);
+            s_jacc[(0 * ROWS + row) * SYM_TJ + c * 16 + q] = aj0;
+            s_jacc[(1 * ROWS + row) * SYM_TJ + c * 16 + q] = aj1;
+            s_jacc[(2 * ROWS + row) * SYM_TJ + c * 16 + q] = aj2;
+        }
+        __syncthreads();
+        if (tid < SYM_TJ) {
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                float sum = 0.0f;
+#pragma unroll
+                for (int r = 0; r < ROWS; ++r) sum += s_jacc[(k * ROWS + r) * SYM_TJ + tid];
+                jpart[((size_t)k * sh.nb + ib) * (size_t)sh.lmax + (size_t)(pt + tid)] = sum;
+            }
+        }
+    }
+    lanes_store<1>(L, n, s, pc.alpha_sum, near_slot, BLOCK, partial);
+}
+
+// out[k n + q] = alpha_sum * (sum of the j-side partials of particle q), FP64,
+// in a fixed order (blocks I = J_q - 1, J_q - 2, ..., then the antipode).
+__global__ void __launch_bounds__(256)
+k_fold_sym(const float* __restrict__ jpart, int n, int block, SymShape sh, double alpha_sum,
+           double* __restrict__ out)
+{
+    const int q = blockIdx.x * 256 + threadIdx.x;
+    if (q >= n) return;
+    const int Jq = q / block, o = q - Jq * block;
+    const int nb = sh.nb, half = nb >> 1;
+    const size_t cs = (size_t)nb * (size_t)sh.lmax;
+    double v0 = 0.0, v1 = 0.0, v2 = 0.0;
+    for (int d = 1; d <= sh.h; ++d) {
+        const int I = (Jq - d + nb) % nb;
+        const size_t at = (size_t)I * sh.lmax + (size_t)(d - 1) * block + o;
+        v0 += (double)jpart[at];
+        v1 += (double)jpart[cs + at];
+        v2 += (double)jpart[2 * cs + at];
+    }
+    if (sh.extra) {
+        const int I = (Jq + half) % nb;
+        if (I < half) {
+            const size_t at = (size_t)I * sh.lmax + (size_t)sh.h * block + o;
+            v0 += (double)jpart[at];
+            v1 += (double)jpart[cs + at];
+            v2 += (double)jpart[2 * cs + at];
+        }
+    }
+    out[q] = alpha_sum * v0;
+    out[(size_t)n + q] = alpha_sum * v1;
+    out[2 * (size_t)n + q] = alpha_sum * v2;
+}
+
 // ---------------------------------------------------------------- FP64 path
 
 template <int TENSOR, int BLOCK, bool PER>
@@ -584,11 +1004,50 @@ static hipError_t launch_f32_t(const PairLaunch& L, const float4* pos, const flo
     return hipGetLastError();
 }
 
+template <int TENSOR, int ACC, int BLOCK>
+static hipError_t launch_f32_sym(const PairLaunch& L, const float4* pos, const float4* frc,
+                                 const double* x64, int n, const PairConst& pc, double* partial,
+                                 hipStream_t st)
+{
+    const SymShape sh = sym_shape_of(L, n);
+    float* jpart = (float*)((char*)partial + sym_jpart_offset(L, n));
+    dim3 grid(sh.nb * sh.isplits + sh.nb), block(BLOCK);
+    if (pc.box > 0.0)
+        hipLaunchKernelGGL((k_pair_f32_sym<TENSOR, ACC, BLOCK, true>), grid, block, 0, st, pos, frc,
+                           x64, n, sh, pc, partial, jpart);
+    else
+        hipLaunchKernelGGL((k_pair_f32_sym<TENSOR, ACC, BLOCK, false>), grid, block, 0, st, pos,
+                           frc, x64, n, sh, pc, partial, jpart);
+    return hipGetLastError();
+}
+
+hipError_t launch_pair_fold(const PairLaunch& L, int n, const PairConst& pc, double* partial,
+                            hipStream_t st)
+{
+    if (L.variant != 2) return hipSuccess;
+    const SymShape sh = sym_shape_of(L, n);
+    const float* jpart = (const float*)((const char*)partial + sym_jpart_offset(L, n));
+    hipLaunchKernelGGL(k_fold_sym, dim3((n + 255) / 256), dim3(256), 0, st, jpart, n, L.block, sh,
+                       pc.alpha_sum, partial + (size_t)(sh.isplits + 1) * 3 * (size_t)n);
+    return hipGetLastError();
+}
+
 template <int TENSOR, int ACC>
 static hipError_t launch_f32_b(const PairLaunch& L, const float4* pos, const float4* frc,
                                const double* x64, int n, const PairConst& pc, double* partial,
                                hipStream_t st)
 {
+    if (L.variant == 2) {
+        if constexpr (ACC == 0 || ACC == 4 || ACC == 8) {
+            if (L.block == 128 && L.ilp == 1)
+                return launch_f32_sym<TENSOR, ACC, 128>(L, pos, frc, x64, n, pc, partial, st);
+            if (L.block == 256 && L.ilp == 1)
+                return launch_f32_sym<TENSOR, ACC, 256>(L, pos, frc, x64, n, pc, partial, st);
+            if (L.block == 512 && L.ilp == 1)
+                return launch_f32_sym<TENSOR, ACC, 512>(L, pos, frc, x64, n, pc, partial, st);
+        }
+        return hipErrorInvalidValue;
+    }
 #define SD_CASE(B, I)                                                                        \
     if (L.block == B && L.ilp == I)                                                          \
         return launch_f32_t<TENSOR, ACC, B, I>(L, pos, frc, x64, n, pc, partial, st);

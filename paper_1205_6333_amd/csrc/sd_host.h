@@ -42,6 +42,10 @@ int device_cus();
 sd_status ws_get(int which, size_t bytes, void** out);
 
 sd_kernel_config default_config(int32_t prec, int64_t n);
+// Whether the j-side workspace of the pair-symmetric kernel (variant 2) for n
+// particles in blocks of `block` stays within SYM_WORKSPACE_CAP bytes.
+constexpr size_t SYM_WORKSPACE_CAP = (size_t)1 << 30;
+bool sym_fits(int64_t n, int block);
 sd_kernel_config choose_config(int32_t prec, int64_t n);
 void set_tuned_config(int32_t prec, int64_t n, const sd_kernel_config& c);
 sd_status check_config(int32_t prec, const sd_kernel_config& c);

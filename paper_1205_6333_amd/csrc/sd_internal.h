@@ -65,7 +65,7 @@ constexpr double NEAR_EPS = 1e-3;
 PairConst make_pair_const(double a, double eta, int tensor, int overlap, double box);
 
 struct PairLaunch {
-    int variant;   // 0 LDS tiles, 1 scalar-cache j stream
+    int variant;   // 0 LDS tiles, 1 scalar-cache j stream, 2 pair symmetry (FP32 only)
     int block;     // threads per work-group
     int splits;    // number of j-range splits actually launched
     int jchunk;    // particles j per split (multiple of block)
@@ -75,6 +75,22 @@ struct PairLaunch {
 
 // Shape the launch for n particles from a requested configuration.
 PairLaunch shape_pair_launch(int n, int variant, int block, int splits, int ilp);
+
+// Block schedule of variant 2 (each pair of distinct blocks once, see
+// k_pair_f32_sym): nb blocks of `block` particles; i-block I takes the h
+// blocks after it (mod nb) and, when nb is even (extra = 1), block I + nb/2
+// if I < nb/2; that virtual j range (at most lmax positions) is cut into
+// isplits splits of chunk positions.  Partial rows: isplits symmetric
+// splits, one row of the one-sided diagonal blocks, one row of the folded j
+// side, so PairLaunch.splits = isplits + 2.  After the rows (256-byte
+// aligned) the workspace holds the FP32 j-side partials, 3 * nb * lmax floats.
+struct SymShape {
+    int nb, h, extra, lmax, chunk, isplits;
+};
+SymShape sym_shape(int n, int block, int splits);
+SymShape sym_shape_of(const PairLaunch& L, int n);
+size_t sym_jpart_floats(const SymShape& sh);
+size_t sym_jpart_offset(const PairLaunch& L, int64_t n);
 
 // Pair kernels: partial[(s*3 + k)*n + i] = sum over split s of the pair terms
 // (self excluded), FP64 output.
@@ -86,6 +102,11 @@ hipError_t launch_pair_f32(const PairLaunch& L, int tensor, int acc, const float
                            double* partial, hipStream_t st);
 hipError_t launch_pair_f64(const PairLaunch& L, int tensor, const double4* pos, const double4* frc,
                            int n, const PairConst& pc, double* partial, hipStream_t st);
+// Variant 2 only (a no-op otherwise): adds the j-side partials the pair kernel
+// left in the workspace into the last partial row.  Enqueue after the pair
+// kernel, before anything reads the partial rows.
+hipError_t launch_pair_fold(const PairLaunch& L, int n, const PairConst& pc, double* partial,
+                            hipStream_t st);
 
 // v_i = mu0 F_i + sum_s partial_s (fixed order).
 hipError_t launch_merge_f32(const double* partial, int splits, int n, const float4* frc, double mu0,

@@ -85,7 +85,10 @@ def test_argument_errors_before_device_work(L):
 
 def test_kernel_config_validation(L):
     from paper_1205_6333_amd import binding as b
-    bad = [dict(variant=2, block=256, splits=1, ilp=1, kahan_block=4),
+    bad = [dict(variant=3, block=256, splits=1, ilp=1, kahan_block=4),
+           dict(variant=2, block=64, splits=1, ilp=1, kahan_block=4),
+           dict(variant=2, block=256, splits=1, ilp=2, kahan_block=4),
+           dict(variant=2, block=256, splits=1, ilp=1, kahan_block=2),
            dict(variant=0, block=96, splits=1, ilp=1, kahan_block=4),
            dict(variant=0, block=256, splits=0, ilp=1, kahan_block=4),
            dict(variant=0, block=256, splits=1, ilp=3, kahan_block=4),
@@ -96,6 +99,11 @@ def test_kernel_config_validation(L):
     with pytest.raises(b.SdError):
         b.sd_set_kernel_config(b.SD_FP64, dict(variant=1, block=256, splits=1, ilp=1,
                                                kahan_block=0))
+    with pytest.raises(b.SdError):
+        b.sd_set_kernel_config(b.SD_FP64, dict(variant=2, block=256, splits=1, ilp=1,
+                                               kahan_block=0))
+    b.sd_set_kernel_config(b.SD_FP32_KAHAN, dict(variant=2, block=128, splits=3, ilp=1,
+                                                 kahan_block=8))
     with pytest.raises(b.SdError):
         b.sd_set_kernel_config(b.SD_FP32_PLAIN, dict(variant=0, block=256, splits=1, ilp=1,
                                                      kahan_block=4))
