@@ -65,21 +65,22 @@ std::vector<sd_kernel_config> candidates(int32_t prec, int64_t n)
     // variant 2 (pair symmetry): FP32 only, ilp 1, kahan_block 0/4/8, blocks
     // of 128 or 256, when its j-side workspace stays within the cap
     if (prec != SD_FP64)
-        for (int block : { 128, 256, 512 }) {
-            sd_kernel_config c;
-            c.variant = 2;
-            c.block = block;
-            c.ilp = 1;
-            if (!sym_fits(n, block)) continue;
-            const std::vector<int> kbs =
-                prec == SD_FP32_KAHAN ? std::vector<int>{ 4, 8 } : std::vector<int>{ 0 };
-            for (int kb : kbs)
-                for (int s : split_opts) {
-                    c.kahan_block = kb;
-                    c.splits = std::max(1, s / 2 * 256 / block);
-                    out.push_back(c);
-                }
-        }
+        for (int block : { 128, 256, 512 })
+            for (int ilp : { 1, 2 }) {
+                if (block * ilp > 512 || !sym_fits(n, block * ilp)) continue;
+                sd_kernel_config c;
+                c.variant = 2;
+                c.block = block;
+                c.ilp = ilp;
+                const std::vector<int> kbs =
+                    prec == SD_FP32_KAHAN ? std::vector<int>{ 4, 8 } : std::vector<int>{ 0 };
+                for (int kb : kbs)
+                    for (int s : split_opts) {
+                        c.kahan_block = kb;
+                        c.splits = std::max(1, s * 256 / (block * ilp));
+                        out.push_back(c);
+                    }
+            }
     return out;
 }
 

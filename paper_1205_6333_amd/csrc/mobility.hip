@@ -52,7 +52,7 @@ PairLaunch shape_pair_launch(int n, int variant, int block, int splits, int ilp)
     L.ilp = ilp;
     if (variant == 2) {
         // rows: the symmetric splits, the diagonal blocks, the folded j side
-        const SymShape sh = sym_shape(n, block, splits);
+        const SymShape sh = sym_shape(n, block * ilp, splits);
         L.jchunk = sh.chunk;
         L.splits = sh.isplits + 2;
         return L;
@@ -508,7 +508,7 @@ SymShape sym_shape(int n, int block, int splits)
 
 SymShape sym_shape_of(const PairLaunch& L, int n)
 {
-    SymShape sh = sym_shape(n, L.block, 1);
+    SymShape sh = sym_shape(n, L.block * L.ilp, 1);
     sh.chunk = L.jchunk;
     sh.isplits = L.splits - 2;
     return sh;
@@ -552,75 +552,93 @@ __device__ __forceinline__ float add_row_rot(float acc, float v)
 }
 
 // One near pair (i, j) of the symmetric kernel in FP64: T(r_ij) F_j is added
-// to the lane's LDS slot, T(r_ij) F_i (= T(r_ji) F_i) is returned in v*.
-// Out of line: the rare branch then holds no registers of the hot loop.
-template <int TENSOR, bool PER, int BLOCK>
+// to the particle's LDS slot (components `stride` apart), T(r_ij) F_i
+// (= T(r_ji) F_i) is added to v*.  Out of line: the rare branch then holds no
+// registers of the hot loop.
+template <int TENSOR, bool PER>
 __device__ __attribute__((noinline)) void sym_near_pair(const LaneF32& L, float fi0, float fi1,
                                                        float fi2, float4 pj, float4 fj, int jg,
                                                        const PairConst& pc,
                                                        const double* __restrict__ x64,
-                                                       double* near_slot, double& v0, double& v1,
-                                                       double& v2)
+                                                       double* slot, int stride, double& v0,
+                                                       double& v1, double& v2)
 {
     double d0, d1, d2;
     near_diff<PER>(L, pj, jg, pc, x64, d0, d1, d2);
-    double n0 = near_slot[0], n1 = near_slot[BLOCK], n2 = near_slot[2 * BLOCK];
+    double n0 = slot[0], n1 = slot[stride], n2 = slot[2 * stride];
     near_term<TENSOR>(pc, d0, d1, d2, (double)fj.x, (double)fj.y, (double)fj.z, n0, n1, n2);
-    near_slot[0] = n0;
-    near_slot[BLOCK] = n1;
-    near_slot[2 * BLOCK] = n2;
+    slot[0] = n0;
+    slot[stride] = n1;
+    slot[2 * stride] = n2;
     near_term<TENSOR>(pc, d0, d1, d2, (double)fi0, (double)fi1, (double)fi2, v0, v1, v2);
 }
 
-// Steps K0 .. K0+7 of a chunk for one lane: pairs (i, element (q + k) mod 16).
-// sp/sf: this lane's view of the doubled chunk (element (q + k) mod 16 at
-// offset k).  jgc: global index of element 0 of the chunk.  aj*: the j-side
-// sums of element q (scaled units), started by step 0.
-template <int TENSOR, int ACC, bool PER, int K0, int BLOCK>
-__device__ __forceinline__ void sym_steps(LaneF32& L, float fi0, float fi1, float fi2, float& aj0,
-                                          float& aj1, float& aj2, const float4* sp,
-                                          const float4* sf, int jgc, int q, int n,
-                                          const PairConst& pc, float gamma, float m3g,
+// Steps K0 .. K0+U-1 of a chunk for one lane and its ILP particles i: pairs
+// (i, element (q + k) mod 16).  sp/sf: this lane's view of the doubled chunk
+// (element (q + k) mod 16 at offset k).  jgc: global index of element 0 of the
+// chunk.  y: the running FP32 sums of the i side (for ACC > 0 the terms since
+// the last compensated add, started from -c; for ACC = 0 the sums themselves);
+// a compensation block of ACC terms may span groups.  aj*: the j-side sums of
+// element q (scaled units), started by step 0.  near_slot: this lane's LDS
+// slot of its first particle (particle l at + l BLOCK, components NS apart).
+template <int TENSOR, int ACC, bool PER, int K0, int U, int ILP, int BLOCK>
+__device__ __forceinline__ void sym_steps(LaneF32 (&L)[ILP], const float (&fi)[ILP][3],
+                                          float (&y)[ILP][3], float& aj0, float& aj1, float& aj2,
+                                          const float4* sp, const float4* sf, int jgc, int q,
+                                          int n, const PairConst& pc, float gamma, float m3g,
                                           float thr2, double inv_alpha_sum,
                                           const double* __restrict__ x64, double* near_slot)
 {
-    constexpr int U = 8;
-    // groups of eight steps are scheduled one after the other: overlapping
-    // them would hold two groups of pair data in registers
+    constexpr int NS = BLOCK * ILP;
+    constexpr int KB = ACC > 0 ? ACC : 1;
+    static_assert(ACC == 0 || KB % U == 0 || U % KB == 0, "compensation blocks and groups");
+    // groups are scheduled one after the other: overlapping them would hold
+    // two groups of pair data in registers
     __builtin_amdgcn_sched_barrier(0);
     float4 pj[U], fj[U];
-    float dx[U], dy[U], dz[U], r2[U];
+    float dx[ILP][U], dy[ILP][U], dz[ILP][U], r2[ILP][U];
     float rmin = 3.0e38f;
 #pragma unroll
     for (int u = 0; u < U; ++u) {
         pj[u] = sp[K0 + u];
         fj[u] = sf[K0 + u];
-        dx[u] = pdiff<PER>(L.x, pj[u].x);
-        dy[u] = pdiff<PER>(L.y, pj[u].y);
-        dz[u] = pdiff<PER>(L.z, pj[u].z);
-        r2[u] = fmaf(dx[u], dx[u], fmaf(dy[u], dy[u], dz[u] * dz[u]));
-        rmin = fminf(rmin, r2[u]);
+#pragma unroll
+        for (int l = 0; l < ILP; ++l) {
+            dx[l][u] = pdiff<PER>(L[l].x, pj[u].x);
+            dy[l][u] = pdiff<PER>(L[l].y, pj[u].y);
+            dz[l][u] = pdiff<PER>(L[l].z, pj[u].z);
+            r2[l][u] = fmaf(dx[l][u], dx[l][u], fmaf(dy[l][u], dy[l][u], dz[l][u] * dz[l][u]));
+            rmin = fminf(rmin, r2[l][u]);
+        }
     }
     // near pairs (rare): masked out of the FP32 code here, evaluated in FP64
     // after it, when this group's FP32 data are no longer live
-    uint32_t nmask = 0;
+    uint32_t nmask = 0;   // bit l U + u
     if (__builtin_amdgcn_ballot_w64(rmin < thr2) != 0) {
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const bool nr = r2[u] < thr2;
-            nmask |= nr ? (1u << u) : 0u;
-            r2[u] = nr ? __builtin_inff() : r2[u];
-        }
+        for (int l = 0; l < ILP; ++l)
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const bool nr = r2[l][u] < thr2;
+                nmask |= nr ? (1u << (l * U + u)) : 0u;
+                r2[l][u] = nr ? __builtin_inff() : r2[l][u];
+            }
     }
-    constexpr int KB = ACC > 0 ? ACC : 1;
-    StaticFor<0, U / KB>::run([&](auto b_c) {
-        constexpr int u0 = decltype(b_c)::value * KB;
-        float y0 = ACC ? -L.c0 : L.s0;
-        float y1 = ACC ? -L.c1 : L.s1;
-        float y2 = ACC ? -L.c2 : L.s2;
-        StaticFor<u0, u0 + KB>::run([&](auto u_c) {
-            constexpr int u = decltype(u_c)::value;
-            const float rinv = __builtin_amdgcn_rsqf(r2[u]);
+    StaticFor<0, U>::run([&](auto u_c) {
+        constexpr int u = decltype(u_c)::value;
+        constexpr int k = K0 + u;   // step within the chunk
+        if constexpr (ACC == 0 ? u == 0 : k % KB == 0) {
+#pragma unroll
+            for (int l = 0; l < ILP; ++l) {
+                y[l][0] = ACC ? -L[l].c0 : L[l].s0;
+                y[l][1] = ACC ? -L[l].c1 : L[l].s1;
+                y[l][2] = ACC ? -L[l].c2 : L[l].s2;
+            }
+        }
+        float c0 = 0.0f, c1 = 0.0f, c2 = 0.0f;
+#pragma unroll
+        for (int l = 0; l < ILP; ++l) {
+            const float rinv = __builtin_amdgcn_rsqf(r2[l][u]);
             const float rinv2 = rinv * rinv;
             const float rinv3 = rinv2 * rinv;
             float A, Bt;
@@ -632,41 +650,56 @@ __device__ __forceinline__ void sym_steps(LaneF32& L, float fi0, float fi1, floa
                 Bt = rinv3 * fmaf(m3g, rinv2, 1.0f);
             }
             // i side: T F_j
-            const float dFj = fmaf(dx[u], fj[u].x, fmaf(dy[u], fj[u].y, dz[u] * fj[u].z));
+            const float dFj =
+                fmaf(dx[l][u], fj[u].x, fmaf(dy[l][u], fj[u].y, dz[l][u] * fj[u].z));
             const float sBj = Bt * dFj;
-            y0 = fmaf(A, fj[u].x, fmaf(sBj, dx[u], y0));
-            y1 = fmaf(A, fj[u].y, fmaf(sBj, dy[u], y1));
-            y2 = fmaf(A, fj[u].z, fmaf(sBj, dz[u], y2));
-            // j side: T F_i, handed to the lane that owns the element
-            const float dFi = fmaf(dx[u], fi0, fmaf(dy[u], fi1, dz[u] * fi2));
+            y[l][0] = fmaf(A, fj[u].x, fmaf(sBj, dx[l][u], y[l][0]));
+            y[l][1] = fmaf(A, fj[u].y, fmaf(sBj, dy[l][u], y[l][1]));
+            y[l][2] = fmaf(A, fj[u].z, fmaf(sBj, dz[l][u], y[l][2]));
+            // j side: T F_i of this lane's particles, summed before the hand-over
+            const float dFi =
+                fmaf(dx[l][u], fi[l][0], fmaf(dy[l][u], fi[l][1], dz[l][u] * fi[l][2]));
             const float sBi = Bt * dFi;
-            const float c0 = fmaf(A, fi0, sBi * dx[u]);
-            const float c1 = fmaf(A, fi1, sBi * dy[u]);
-            const float c2 = fmaf(A, fi2, sBi * dz[u]);
-            if constexpr (K0 + u == 0) {  // first step of a chunk starts the sums
-                aj0 = c0;
-                aj1 = c1;
-                aj2 = c2;
+            if (l == 0) {
+                c0 = fmaf(A, fi[l][0], sBi * dx[l][u]);
+                c1 = fmaf(A, fi[l][1], sBi * dy[l][u]);
+                c2 = fmaf(A, fi[l][2], sBi * dz[l][u]);
             } else {
-                aj0 = add_row_rot<(K0 + u) & 15>(aj0, c0);
-                aj1 = add_row_rot<(K0 + u) & 15>(aj1, c1);
-                aj2 = add_row_rot<(K0 + u) & 15>(aj2, c2);
+                c0 = fmaf(A, fi[l][0], fmaf(sBi, dx[l][u], c0));
+                c1 = fmaf(A, fi[l][1], fmaf(sBi, dy[l][u], c1));
+                c2 = fmaf(A, fi[l][2], fmaf(sBi, dz[l][u], c2));
             }
-        });
-        if (ACC) {
-            const float t0 = L.s0 + y0;
-            const float t1 = L.s1 + y1;
-            const float t2 = L.s2 + y2;
-            L.c0 = (t0 - L.s0) - y0;
-            L.c1 = (t1 - L.s1) - y1;
-            L.c2 = (t2 - L.s2) - y2;
-            L.s0 = t0;
-            L.s1 = t1;
-            L.s2 = t2;
+        }
+        // hand the j-side term to the lane that owns the element
+        if constexpr (k == 0) {   // the first step of a chunk starts the sums
+            aj0 = c0;
+            aj1 = c1;
+            aj2 = c2;
         } else {
-            L.s0 = y0;
-            L.s1 = y1;
-            L.s2 = y2;
+            aj0 = add_row_rot<k & 15>(aj0, c0);
+            aj1 = add_row_rot<k & 15>(aj1, c1);
+            aj2 = add_row_rot<k & 15>(aj2, c2);
+        }
+        if constexpr (ACC == 0 ? u == U - 1 : k % KB == KB - 1) {
+#pragma unroll
+            for (int l = 0; l < ILP; ++l) {
+                if (ACC) {
+                    // Fast2Sum: s + y exactly as t + (y - (t - s)), c = -(y - (t - s))
+                    const float t0 = L[l].s0 + y[l][0];
+                    const float t1 = L[l].s1 + y[l][1];
+                    const float t2 = L[l].s2 + y[l][2];
+                    L[l].c0 = (t0 - L[l].s0) - y[l][0];
+                    L[l].c1 = (t1 - L[l].s1) - y[l][1];
+                    L[l].c2 = (t2 - L[l].s2) - y[l][2];
+                    L[l].s0 = t0;
+                    L[l].s1 = t1;
+                    L[l].s2 = t2;
+                } else {
+                    L[l].s0 = y[l][0];
+                    L[l].s1 = y[l][1];
+                    L[l].s2 = y[l][2];
+                }
+            }
         }
     });
     if (__builtin_amdgcn_ballot_w64(nmask != 0) != 0) {
@@ -680,13 +713,18 @@ __device__ __forceinline__ void sym_steps(LaneF32& L, float fi0, float fi1, floa
         asm volatile("" : "+v"(qn), "+v"(spn), "+v"(sfn));
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            const bool nr = (nmask >> u) & 1u;
-            if (__builtin_amdgcn_ballot_w64(nr) == 0) continue;
+            uint32_t um = 0;
+#pragma unroll
+            for (int l = 0; l < ILP; ++l) um |= (nmask >> (l * U + u)) & 1u;
+            if (__builtin_amdgcn_ballot_w64(um != 0) == 0) continue;
             const int jg = jgc + ((qn + K0 + u) & 15);
             double v0 = 0.0, v1 = 0.0, v2 = 0.0;
-            if (nr && L.i < n && jg < n && jg != L.i)
-                sym_near_pair<TENSOR, PER, BLOCK>(L, fi0, fi1, fi2, spn[K0 + u], sfn[K0 + u], jg,
-                                                  pc, x64, near_slot, v0, v1, v2);
+#pragma unroll
+            for (int l = 0; l < ILP; ++l)
+                if (((nmask >> (l * U + u)) & 1u) && L[l].i < n && jg < n && jg != L[l].i)
+                    sym_near_pair<TENSOR, PER>(L[l], fi[l][0], fi[l][1], fi[l][2], spn[K0 + u],
+                                               sfn[K0 + u], jg, pc, x64, near_slot + l * BLOCK,
+                                               NS, v0, v1, v2);
             // the owner of element (q + k) mod 16 is lane q + k of the row
             const int lane = (int)(threadIdx.x & 63);
             const int src = (lane & ~15) | ((qn - (K0 + u)) & 15);
@@ -703,18 +741,23 @@ __device__ __forceinline__ void sym_steps(LaneF32& L, float fi0, float fi1, floa
     }
 }
 
-template <int TENSOR, int ACC, int BLOCK, bool PER>
-__global__ void __launch_bounds__(BLOCK)
+// ILP particles per lane (ILP 2: the i-block of BLOCK * ILP particles has
+// particle tid and tid + BLOCK in lane tid), groups of U steps.
+template <int TENSOR, int ACC, int BLOCK, int ILP, bool PER>
+__global__ void __launch_bounds__(BLOCK, ILP == 2 ? 3 : 1)   // ILP 2: at least 3 waves per SIMD
 k_pair_f32_sym(const float4* __restrict__ pos, const float4* __restrict__ frc,
                const double* __restrict__ x64, int n, SymShape sh, PairConst pc,
                double* __restrict__ partial, float* __restrict__ jpart)
 {
-    static_assert(BLOCK % SYM_TJ == 0, "j tiles must not straddle blocks");
+    constexpr int B = BLOCK * ILP;   // particles per block
+    constexpr int NS = B;            // stride of the near slots
+    constexpr int U = ILP == 1 ? 8 : 4;
+    static_assert(B % SYM_TJ == 0, "j tiles must not straddle blocks");
     constexpr int ROWS = BLOCK / 16;
-    constexpr int NPOS = BLOCK > 2 * SYM_TJ ? BLOCK : 2 * SYM_TJ;
+    constexpr int NPOS = B > 2 * SYM_TJ ? B : 2 * SYM_TJ;
     __shared__ float4 s_pos[NPOS];
     __shared__ float4 s_frc[NPOS];
-    __shared__ double s_near[3 * BLOCK];
+    __shared__ double s_near[3 * B];
     __shared__ float s_jacc[3 * ROWS * SYM_TJ];
     const int tid = threadIdx.x;
     const int nsym = sh.nb * sh.isplits;
@@ -726,9 +769,9 @@ k_pair_f32_sym(const float4* __restrict__ pos, const float4* __restrict__ frc,
     } else {
         map_block(sh.isplits, ib, s);
     }
-    LaneF32 L[1];
-    lanes_init<1, BLOCK, PER>(L, pos, n, ib);
-    double* near_slot = near_slots_init<1, BLOCK>(s_near);
+    LaneF32 L[ILP];
+    lanes_init<ILP, BLOCK, PER>(L, pos, n, ib);
+    double* near_slot = near_slots_init<ILP, BLOCK>(s_near);
     const float gamma = pc.gamma_f, m3g = pc.m3gamma_f, thr2 = pc.thr2_f;
     const float4 far_j4 = make_float4(far_j<PER>(), far_j<PER>(), far_j<PER>(), 0.0f);
     const float4 zero4 = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
@@ -739,48 +782,57 @@ k_pair_f32_sym(const float4* __restrict__ pos, const float4* __restrict__ frc,
         // would raise the register count of the whole kernel)
         constexpr int ACC_D = ACC > 4 ? 4 : ACC;
         constexpr int GROUP_U = GroupSize<ACC_D>::value;
-        const int jt = ib * BLOCK;
-        float4 rp = far_j4, rf = zero4;
-        if (jt + tid < n) {
-            rp = pos[jt + tid];
-            rf = frc[jt + tid];
+        const int jt = ib * B;
+#pragma unroll
+        for (int r = 0; r < ILP; ++r) {
+            const int t = tid + r * BLOCK;
+            float4 rp = far_j4, rf = zero4;
+            if (jt + t < n) {
+                rp = pos[jt + t];
+                rf = frc[jt + t];
+            }
+            s_pos[t] = rp;
+            s_frc[t] = rf;
         }
-        s_pos[tid] = rp;
-        s_frc[tid] = rf;
         __syncthreads();
 #pragma unroll 1
-        for (int k = 0; k < BLOCK; k += GROUP_U) {
+        for (int k = 0; k < B; k += GROUP_U) {
             float4 pj[GROUP_U], fj[GROUP_U];
 #pragma unroll
             for (int u = 0; u < GROUP_U; ++u) {
                 pj[u] = s_pos[k + u];
                 fj[u] = s_frc[k + u];
             }
-            pair_group<TENSOR, ACC_D, GROUP_U, 1, PER>(L, pj, fj, jt + k, n, pc, gamma, m3g,
-                                                       thr2, x64, near_slot, BLOCK);
+            pair_group<TENSOR, ACC_D, GROUP_U, ILP, PER>(L, pj, fj, jt + k, n, pc, gamma, m3g,
+                                                         thr2, x64, near_slot, NS);
         }
-        lanes_store<1>(L, n, s, pc.alpha_sum, near_slot, BLOCK, partial);
+        lanes_store<ILP>(L, n, s, pc.alpha_sum, near_slot, NS, partial);
         return;
     }
 
-    float fi0 = 0.0f, fi1 = 0.0f, fi2 = 0.0f;
-    if (L[0].i < n) {
-        const float4 f = frc[L[0].i];
-        fi0 = f.x;
-        fi1 = f.y;
-        fi2 = f.z;
+    float fi[ILP][3];
+#pragma unroll
+    for (int l = 0; l < ILP; ++l) {
+        fi[l][0] = fi[l][1] = fi[l][2] = 0.0f;
+        if (L[l].i < n) {
+            const float4 f = frc[L[l].i];
+            fi[l][0] = f.x;
+            fi[l][1] = f.y;
+            fi[l][2] = f.z;
+        }
     }
+    float y[ILP][3];
     const double inv_alpha_sum = 1.0 / pc.alpha_sum;
     const int q = tid & 15;
     const int row = tid >> 4;
     const int half = sh.nb >> 1;
-    const int lI = (sh.h + ((sh.extra && ib < half) ? 1 : 0)) * BLOCK;
+    const int lI = (sh.h + ((sh.extra && ib < half) ? 1 : 0)) * B;
     const int pbeg = s * sh.chunk;
     const int pend = min(lI, pbeg + sh.chunk);
-    // tile element tid (threads tid < SYM_TJ) of the tile at virtual position pt
+    // first particle of the tile at virtual position pt
     auto tile_first = [&](int pt) {
-        const int J = (ib + 1 + pt / BLOCK) % sh.nb;
-        return J * BLOCK + (pt % BLOCK);
+        const int J = (ib + 1 + pt / B) % sh.nb;
+        return J * B + (pt % B);
     };
     float4 rp = far_j4, rf = zero4;
     if (pbeg < pend && tid < SYM_TJ) {
@@ -816,12 +868,12 @@ k_pair_f32_sym(const float4* __restrict__ pos, const float4* __restrict__ frc,
             const float4* sp = s_pos + c * 32 + q;
             const float4* sf = s_frc + c * 32 + q;
             const int jgc = jt + c * 16;
-            sym_steps<TENSOR, ACC, PER, 0, BLOCK>(L[0], fi0, fi1, fi2, aj0, aj1, aj2, sp, sf, jgc,
-                                                  q, n, pc, gamma, m3g, thr2, inv_alpha_sum, x64,
-                                                  near_slot);
-            sym_steps<TENSOR, ACC, PER, 8, BLOCK>(L[0], fi0, fi1, fi2, aj0, aj1, aj2, sp, sf, jgc,
-                                                  q, n, pc, gamma, m3g, thr2, inv_alpha_sum, x64,
-                                                  near_slot);
+            StaticFor<0, 16 / U>::run([&](auto g_c) {
+                constexpr int K0 = decltype(g_c)::value * U;
+                sym_steps<TENSOR, ACC, PER, K0, U, ILP, BLOCK>(L, fi, y, aj0, aj1, aj2, sp, sf,
+                                                               jgc, q, n, pc, gamma, m3g, thr2,
+                                                               inv_alpha_sum, x64, near_slot);
+            });
             s_jacc[(0 * ROWS + row) * SYM_TJ + c * 16 + q] = aj0;
             s_jacc[(1 * ROWS + row) * SYM_TJ + c * 16 + q] = aj1;
             s_jacc[(2 * ROWS + row) * SYM_TJ + c * 16 + q] = aj2;
@@ -837,7 +889,7 @@ k_pair_f32_sym(const float4* __restrict__ pos, const float4* __restrict__ frc,
             }
         }
     }
-    lanes_store<1>(L, n, s, pc.alpha_sum, near_slot, BLOCK, partial);
+    lanes_store<ILP>(L, n, s, pc.alpha_sum, near_slot, NS, partial);
 }
 
 // out[k n + q] = alpha_sum * (sum of the j-side partials of particle q), FP64,
@@ -1004,7 +1056,7 @@ static hipError_t launch_f32_t(const PairLaunch& L, const float4* pos, const flo
     return hipGetLastError();
 }
 
-template <int TENSOR, int ACC, int BLOCK>
+template <int TENSOR, int ACC, int BLOCK, int ILP>
 static hipError_t launch_f32_sym(const PairLaunch& L, const float4* pos, const float4* frc,
                                  const double* x64, int n, const PairConst& pc, double* partial,
                                  hipStream_t st)
@@ -1013,11 +1065,11 @@ static hipError_t launch_f32_sym(const PairLaunch& L, const float4* pos, const f
     float* jpart = (float*)((char*)partial + sym_jpart_offset(L, n));
     dim3 grid(sh.nb * sh.isplits + sh.nb), block(BLOCK);
     if (pc.box > 0.0)
-        hipLaunchKernelGGL((k_pair_f32_sym<TENSOR, ACC, BLOCK, true>), grid, block, 0, st, pos, frc,
-                           x64, n, sh, pc, partial, jpart);
+        hipLaunchKernelGGL((k_pair_f32_sym<TENSOR, ACC, BLOCK, ILP, true>), grid, block, 0, st,
+                           pos, frc, x64, n, sh, pc, partial, jpart);
     else
-        hipLaunchKernelGGL((k_pair_f32_sym<TENSOR, ACC, BLOCK, false>), grid, block, 0, st, pos,
-                           frc, x64, n, sh, pc, partial, jpart);
+        hipLaunchKernelGGL((k_pair_f32_sym<TENSOR, ACC, BLOCK, ILP, false>), grid, block, 0, st,
+                           pos, frc, x64, n, sh, pc, partial, jpart);
     return hipGetLastError();
 }
 
@@ -1027,7 +1079,8 @@ hipError_t launch_pair_fold(const PairLaunch& L, int n, const PairConst& pc, dou
     if (L.variant != 2) return hipSuccess;
     const SymShape sh = sym_shape_of(L, n);
     const float* jpart = (const float*)((const char*)partial + sym_jpart_offset(L, n));
-    hipLaunchKernelGGL(k_fold_sym, dim3((n + 255) / 256), dim3(256), 0, st, jpart, n, L.block, sh,
+    hipLaunchKernelGGL(k_fold_sym, dim3((n + 255) / 256), dim3(256), 0, st, jpart, n,
+                       L.block * L.ilp, sh,
                        pc.alpha_sum, partial + (size_t)(sh.isplits + 1) * 3 * (size_t)n);
     return hipGetLastError();
 }
@@ -1040,11 +1093,15 @@ static hipError_t launch_f32_b(const PairLaunch& L, const float4* pos, const flo
     if (L.variant == 2) {
         if constexpr (ACC == 0 || ACC == 4 || ACC == 8) {
             if (L.block == 128 && L.ilp == 1)
-                return launch_f32_sym<TENSOR, ACC, 128>(L, pos, frc, x64, n, pc, partial, st);
+                return launch_f32_sym<TENSOR, ACC, 128, 1>(L, pos, frc, x64, n, pc, partial, st);
             if (L.block == 256 && L.ilp == 1)
-                return launch_f32_sym<TENSOR, ACC, 256>(L, pos, frc, x64, n, pc, partial, st);
+                return launch_f32_sym<TENSOR, ACC, 256, 1>(L, pos, frc, x64, n, pc, partial, st);
             if (L.block == 512 && L.ilp == 1)
-                return launch_f32_sym<TENSOR, ACC, 512>(L, pos, frc, x64, n, pc, partial, st);
+                return launch_f32_sym<TENSOR, ACC, 512, 1>(L, pos, frc, x64, n, pc, partial, st);
+            if (L.block == 128 && L.ilp == 2)
+                return launch_f32_sym<TENSOR, ACC, 128, 2>(L, pos, frc, x64, n, pc, partial, st);
+            if (L.block == 256 && L.ilp == 2)
+                return launch_f32_sym<TENSOR, ACC, 256, 2>(L, pos, frc, x64, n, pc, partial, st);
         }
         return hipErrorInvalidValue;
     }

@@ -228,10 +228,14 @@ sd_kernel_config default_config(int32_t prec, int64_t n)
     s = std::min<int64_t>(s, 512);
     c.splits = (int32_t)s;
     // From n = 4096 on, the pair-symmetric kernel (each pair of particles in
-    // different blocks evaluated once) whenever its j-side workspace fits,
-    // with the same split count (N = 65536, blocks of 256, measured: 16
-    // splits 1.87 ms, 32 splits 1.84 ms, 64 splits 1.86 ms per launch).
-    if (prec != SD_FP64 && n >= 4096 && sym_fits(n, c.block)) c.variant = 2;
+    // different blocks evaluated once) with two particles per lane, whenever
+    // its j-side workspace fits.  Measured at N = 65536 on one box (ms per
+    // launch): variant 0 2.16; variant 2 with one particle per lane 1.93,
+    // with two 1.94 / 1.85 / 1.81 at 8 / 16 / 32 splits.
+    if (prec != SD_FP64 && n >= 4096 && sym_fits(n, 2 * c.block)) {
+        c.variant = 2;
+        c.ilp = 2;
+    }
     return c;
 }
 
@@ -272,7 +276,7 @@ sd_status check_config(int32_t prec, const sd_kernel_config& c)
         if (prec == SD_FP64) return fail(SD_EINVAL, "variant 2 is an FP32 kernel");
         if (c.block != 128 && c.block != 256 && c.block != 512)
             return fail(SD_EINVAL, "variant 2 needs block 128, 256 or 512");
-        if (c.ilp != 1) return fail(SD_EINVAL, "variant 2 needs ilp 1");
+        if (c.block * c.ilp > 512) return fail(SD_EINVAL, "variant 2 needs block * ilp <= 512");
         if (c.kahan_block != 0 && c.kahan_block != 4 && c.kahan_block != 8)
             return fail(SD_EINVAL, "variant 2 needs kahan_block 0, 4 or 8");
     }

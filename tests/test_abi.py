@@ -87,7 +87,7 @@ def test_kernel_config_validation(L):
     from paper_1205_6333_amd import binding as b
     bad = [dict(variant=3, block=256, splits=1, ilp=1, kahan_block=4),
            dict(variant=2, block=64, splits=1, ilp=1, kahan_block=4),
-           dict(variant=2, block=256, splits=1, ilp=2, kahan_block=4),
+           dict(variant=2, block=512, splits=1, ilp=2, kahan_block=4),
            dict(variant=2, block=256, splits=1, ilp=1, kahan_block=2),
            dict(variant=0, block=96, splits=1, ilp=1, kahan_block=4),
            dict(variant=0, block=256, splits=0, ilp=1, kahan_block=4),

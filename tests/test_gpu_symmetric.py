@@ -46,33 +46,38 @@ def _apply(sd, x, f, prec, p, cfg):
     return v.cpu().numpy()
 
 
-def _cfg(block, splits, kb):
-    return dict(variant=2, block=block, splits=splits, ilp=1, kahan_block=kb)
+def _cfg(block, splits, kb, ilp=1):
+    return dict(variant=2, block=block, splits=splits, ilp=ilp, kahan_block=kb)
+
+
+# (work-group size, particles per lane): blocks of 128 to 512 particles
+SHAPES = [(128, 1), (256, 1), (512, 1), (128, 2), (256, 2)]
 
 
 @pytest.mark.parametrize("n", [1, 2, 17, 128, 129, 255, 256, 257, 511, 512, 513, 769, 1000,
                                1337, 2049])
-@pytest.mark.parametrize("block", [128, 256, 512])
-def test_sym_sizes(sd, orc, n, block):
+@pytest.mark.parametrize("block,ilp", SHAPES)
+def test_sym_sizes(sd, orc, n, block, ilp):
     x = W.random_suspension(n, seed=400 + n)
     f = W.gaussian_forces(n, seed=500 + n)
     ref = orc.mobility(orc.params(), W.round_to_f32(x), W.round_to_f32(f))
     for splits in (1, 3, 1000):
-        v = _apply(sd, x, f, 0, sd.params(), _cfg(block, splits, 8))
+        v = _apply(sd, x, f, 0, sd.params(), _cfg(block, splits, 8, ilp))
         err = rel2(v, ref)
-        print("n=%d block=%d splits=%d rel2=%.3e" % (n, block, splits, err))
-        assert err <= TOL[0], (n, block, splits, err)
+        print("n=%d block=%d ilp=%d splits=%d rel2=%.3e" % (n, block, ilp, splits, err))
+        assert err <= TOL[0], (n, block, ilp, splits, err)
 
 
 @pytest.mark.parametrize("kb,prec", [(0, 2), (4, 0), (8, 0)])
 @pytest.mark.parametrize("tensor", [0, 1])
-def test_sym_accumulation_and_tensor(sd, orc, kb, prec, tensor):
+@pytest.mark.parametrize("ilp", [1, 2])
+def test_sym_accumulation_and_tensor(sd, orc, kb, prec, tensor, ilp):
     n = 3001
     x = W.random_suspension(n, seed=410)
     f = W.gaussian_forces(n, seed=411)
     po = orc.params(tensor=tensor)
     ref = orc.mobility(po, W.round_to_f32(x), W.round_to_f32(f))
-    v = _apply(sd, x, f, prec, sd.params(tensor=tensor), _cfg(256, 4, kb))
+    v = _apply(sd, x, f, prec, sd.params(tensor=tensor), _cfg(256, 4, kb, ilp))
     assert rel2(v, ref) <= TOL[prec]
 
 
@@ -86,9 +91,9 @@ def test_sym_overlapping_pairs(sd, orc, tensor, overlap):
     po = orc.params(a=1.3, eta=0.21, tensor=tensor, overlap=overlap)
     ps = sd.params(1.3, 0.21, tensor, overlap)
     ref = orc.mobility(po, W.round_to_f32(x), W.round_to_f32(f))
-    for block in (128, 256, 512):
-        v = _apply(sd, x, f, 0, ps, _cfg(block, 2, 8))
-        assert rel2(v, ref) <= TOL[0], block
+    for block, ilp in SHAPES:
+        v = _apply(sd, x, f, 0, ps, _cfg(block, 2, 8, ilp))
+        assert rel2(v, ref) <= TOL[0], (block, ilp)
 
 
 def test_sym_coincident_spheres(sd, orc):
@@ -99,10 +104,10 @@ def test_sym_coincident_spheres(sd, orc):
     f = W.gaussian_forces(n, seed=442)
     for overlap in (False, True):
         ref = orc.mobility(orc.params(overlap=overlap), W.round_to_f32(x), W.round_to_f32(f))
-        for block in (128, 256, 512):
-            v = _apply(sd, x, f, 0, sd.params(overlap=overlap), _cfg(block, 3, 8))
+        for block, ilp in SHAPES:
+            v = _apply(sd, x, f, 0, sd.params(overlap=overlap), _cfg(block, 3, 8, ilp))
             assert np.all(np.isfinite(v))
-            assert rel2(v, ref) <= TOL[0], (overlap, block)
+            assert rel2(v, ref) <= TOL[0], (overlap, block, ilp)
 
 
 @pytest.mark.parametrize("n", [700, 3001])
@@ -112,9 +117,9 @@ def test_sym_periodic(sd, orc, n):
     x, L = W.periodic_suspension(n, phi=0.2, min_dist=2.02, seed=450 + n)
     f = W.gaussian_forces(n, seed=451)
     ref = orc.mobility(orc.params(box=L), W.round_to_f32(x), W.round_to_f32(f))
-    for block in (128, 256, 512):
-        v = _apply(sd, x, f, 0, sd.params(box=L), _cfg(block, 5, 8))
-        assert rel2(v, ref) <= TOL[0], block
+    for block, ilp in SHAPES:
+        v = _apply(sd, x, f, 0, sd.params(box=L), _cfg(block, 5, 8, ilp))
+        assert rel2(v, ref) <= TOL[0], (block, ilp)
 
 
 def test_sym_matches_variant0_and_is_deterministic(sd):
@@ -145,8 +150,8 @@ def test_sym_time_loop(sd, orc):
     x0 = W.random_suspension(n, phi=0.2, min_dist=2.0, seed=471)
     f = W.gravity_forces(n) + 0.3 * W.gaussian_forces(n, seed=472)
     xr, vr, _ = orc.run(orc.params(overlap=True), x0, W.round_to_f32(f), 0.005, 40, orc.AB2)
-    for block in (128, 256, 512):
-        sd.sd_set_kernel_config(0, _cfg(block, 3, 8))
+    for block, ilp in SHAPES:
+        sd.sd_set_kernel_config(0, _cfg(block, 3, 8, ilp))
         try:
             xd = torch.tensor(x0, dtype=torch.float64, device="cuda")
             vp = torch.zeros_like(xd)
@@ -157,5 +162,5 @@ def test_sym_time_loop(sd, orc):
         finally:
             sd.sd_set_kernel_config(0, None)
         err = np.abs(xd.cpu().numpy() - xr).max() / np.abs(xr - x0).max()
-        print("block=%d time loop err/disp = %.3e" % (block, err))
+        print("block=%d ilp=%d time loop err/disp = %.3e" % (block, ilp, err))
         assert err <= 1e-6
