@@ -61,10 +61,10 @@ METRIC = "G pair-interactions/s of RPY mobility product at N=65536 (FP32-comp vs
 # scaled by what the counter reads for a plain 256 MiB copy (fetch x 2.00,
 # write x 1.00).  Valid only for the kernel source (SHA-1 of mobility.hip) and
 # launch configuration the counters were taken with; otherwise reported as null.
-PMC_TRAFFIC = {"source_sha1": "d93b20b153f4e605b04bda7d8c21f3a1c9c0988b",
+PMC_TRAFFIC = {"source_sha1": "39b4d1c87046f40b6cfd0df0624d9ca24fa4ca25",
                "n": 65536,
-               "config": {"variant": 0, "block": 256, "splits": 32, "ilp": 1, "kahan_block": 8},
-               "fetch_kib": 4683.3, "write_kib": 49152.0, "fetch_scale": 2.0, "write_scale": 1.0}
+               "config": {"variant": 2, "block": 256, "splits": 32, "ilp": 2, "kahan_block": 8},
+               "fetch_kib": 59224.0, "write_kib": 449987.0, "fetch_scale": 2.0, "write_scale": 1.0}
 
 
 def _measured_traffic(n, cfg):
@@ -85,10 +85,10 @@ def _measured_traffic(n, cfg):
 # VALU wave instructions of one product-kernel launch (rocprofv3 SQ_INSTS_VALU,
 # profiles/pair_kernel_f32_n65536_valu_counters.md), same validity rule.
 PMC_VALU = {"source_sha1": PMC_TRAFFIC["source_sha1"], "n": 65536,
-            "config": PMC_TRAFFIC["config"], "valu_wave_instr": 1634484224,
+            "config": PMC_TRAFFIC["config"], "valu_wave_instr": 1204900352,
             # SQ_INSTS_VALU_{ADD,MUL,FMA,TRANS}_F32 per dispatch (wave instructions)
-            "add_f32": 276824064, "mul_f32": 402685952, "fma_f32": 805306368,
-            "trans_f32": 67141632}
+            "add_f32": 190021632, "mul_f32": 319455232, "fma_f32": 622198784,
+            "trans_f32": 33849344}
 
 
 def _measured_valu(n, cfg):
@@ -616,7 +616,8 @@ def main():
                        "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_TFLOPS,
                        "traffic": _measured_traffic(n, cfg),
                        "flop_per_pair": FLOP_PER_PAIR,
-                       "kernel": "pair kernel (k_pair_f32_*)"}
+                       "kernel": "pair kernel (%s)" % ("k_pair_f32_sym" if cfg.get("variant") == 2
+                                                      else "k_pair_f32_lds/smem")}
     valu = _measured_valu(n, cfg)
     if valu is not None:
         instr, flops = valu

@@ -227,12 +227,14 @@ sd_kernel_config default_config(int32_t prec, int64_t n)
     s = std::min<int64_t>(s, tiles);
     s = std::min<int64_t>(s, 512);
     c.splits = (int32_t)s;
-    // From n = 4096 on, the pair-symmetric kernel (each pair of particles in
-    // different blocks evaluated once) with two particles per lane, whenever
-    // its j-side workspace fits.  Measured at N = 65536 on one box (ms per
-    // launch): variant 0 2.16; variant 2 with one particle per lane 1.93,
-    // with two 1.94 / 1.85 / 1.81 at 8 / 16 / 32 splits.
-    if (prec != SD_FP64 && n >= 4096 && sym_fits(n, 2 * c.block)) {
+    // From n = SYM_MIN_N on, the pair-symmetric kernel (each pair of particles
+    // in different blocks evaluated once) with two particles per lane,
+    // whenever its j-side workspace fits.  Measured (ms per product, wall
+    // clock, one box): N = 65536: variant 0 2.14, variant 2 1.83 (32 splits;
+    // one particle per lane 1.96).  N = 16384: variant 0 0.162, variant 2 at
+    // best 0.172; N = 8192: 0.063 vs 0.081; N = 4096: 0.032 vs 0.051 (the
+    // fold and the fixed cost per work-group do not pay off there).
+    if (prec != SD_FP64 && n >= SYM_MIN_N && sym_fits(n, 2 * c.block)) {
         c.variant = 2;
         c.ilp = 2;
     }
