@@ -386,9 +386,12 @@ typedef struct sd_kernel_config {
                              scalar cache, 2 = pair symmetry (FP32 precisions
                              only): every pair of particles in different
                              blocks evaluated once, T(r_ij) F_i handed to j
-                             (block symmetry of M, Sec. 3.3); ilp 1,
-                             kahan_block 0, 4 or 8; library workspace of
-                             about 6 n^2 / block bytes */
+                             (block symmetry of M, Sec. 3.3); block * ilp
+                             <= 512, kahan_block 0, 4 or 8; library
+                             workspace of about 6 n^2 / (block * ilp)
+                             bytes.  The automatic choice takes it from
+                             n = 32768 on (block 256, ilp 2) while that
+                             workspace stays within 1 GiB */
     int32_t block;        /* work-group size (64, 128 or 256; variant 2: 128,
                              256 or 512) */
     int32_t splits;       /* j-range splits (>= 1): extra work-groups per i-block */
