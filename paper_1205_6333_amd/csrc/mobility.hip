@@ -468,16 +468,17 @@ k_pair_f32_smem(const float4* __restrict__ pos, const float4* __restrict__ frc,
 // a pair gives both T(r_ij) F_j for i and T(r_ij) F_i for j.  Variant 2
 // evaluates every pair of particles in different blocks once:
 //
-// Block schedule.  Particles are cut into nb blocks of BLOCK.  Work-group
+// Block schedule.  Particles are cut into nb blocks of B = BLOCK * ILP
+// (ILP particles per lane, see k_pair_f32_sym).  Work-group
 // (I, s) owns i-block I.  The blocks J = I + 1 .. I + h (mod nb), h =
 // (nb - 1) / 2, and, when nb is even, J = I + nb/2 for I < nb/2 only, form a
-// virtual j range p = (J - I - 1 mod nb) BLOCK + offset, cut into splits of
+// virtual j range p = (J - I - 1 mod nb) B + offset, cut into splits of
 // `chunk` positions.  Every unordered pair of distinct blocks is thus taken
 // exactly once.  The diagonal blocks J = I are taken one-sided (every ordered
 // pair, as variant 0) by nb extra work-groups dispatched last.
 //
-// Rows of 16 lanes.  Each 16-lane row of a wave holds 16 particles i, one
-// per lane.  A tile of SYM_TJ particles j is staged in LDS in chunks of 16,
+// Rows of 16 lanes.  Each 16-lane row of a wave holds 16 (ILP 2: 32)
+// particles i, one (two) per lane.  A tile of SYM_TJ particles j is staged in LDS in chunks of 16,
 // each chunk stored twice in a row, so that lane q reads element (q + k) mod
 // 16 of a chunk at the constant offset k.  In step k of a chunk lane q pairs
 // its i with that element; the j-side term goes to the lane that owns the
