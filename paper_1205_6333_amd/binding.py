@@ -251,7 +251,7 @@ def sd_run(x, force, dt: float, steps: int, *, step0: int = 0, v_prev=None,
     _vec4(force, prec, "force")
     if v_prev is not None:
         _vec3(v_prev, n, "v_prev")
-    if checkpoints is not None:
+    if checkpoints is not None and int(checkpoint_every) >= 1:   # else the library says why
         _vec3(checkpoints, n * (steps // checkpoint_every + 1), "checkpoints")
     p = params if params is not None else globals()["params"]()
     check(lib().sd_run(ctypes.byref(p), n, _ptr(x), _ptr(force), _ptr(v_prev), float(dt),
@@ -274,7 +274,7 @@ def sd_run_adjoint(x0, force, dt: float, steps: int, grad_xN, *, checkpoints=Non
         grad_x0 = torch.empty((n, 3), dtype=torch.float64, device=x0.device)
     if grad_force is None:
         grad_force = torch.empty((n, 3), dtype=torch.float64, device=x0.device)
-    if checkpoints is not None:
+    if checkpoints is not None and int(checkpoint_every) >= 1:   # else the library says why
         _vec3(checkpoints, n * (steps // checkpoint_every + 1), "checkpoints")
     p = params if params is not None else globals()["params"]()
     check(lib().sd_run_adjoint(ctypes.byref(p), n, _ptr(x0), _ptr(force), float(dt), int(steps),

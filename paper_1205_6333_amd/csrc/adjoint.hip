@@ -475,7 +475,7 @@ hipError_t launch_adjoint_f64(const PairLaunch& L, int tensor, const double4* po
 static PairLaunch plan_adjoint(int32_t prec, int64_t n)
 {
     sd_kernel_config c = default_config(prec, n);
-    PairLaunch L = shape_pair_launch((int)n, 0, 256, c.splits, 1);
+    PairLaunch L = shape_pair_launch((int)n, 0, 256, c.splits, 1, 0);
     L.acc = 0;
     return L;
 }

@@ -16,6 +16,7 @@
 #include "pair_terms.h"
 #include "sd_internal.h"
 
+#include <algorithm>
 #include <cmath>
 #include <type_traits>
 
@@ -44,16 +45,19 @@ PairConst make_pair_const(double a, double eta, int tensor, int overlap, double 
     return c;
 }
 
-PairLaunch shape_pair_launch(int n, int variant, int block, int splits, int ilp)
+PairLaunch shape_pair_launch(int n, int variant, int block, int splits, int ilp, int cus)
 {
     PairLaunch L;
     L.variant = variant;
     L.block = block;
     L.ilp = ilp;
+    L.acc = 0;
+    L.cus = 0;
     if (variant == 2) {
         // rows: the symmetric splits, the diagonal blocks, the folded j side
-        const SymShape sh = sym_shape(n, block * ilp, splits);
-        L.jchunk = sh.chunk;
+        L.jchunk = splits < 1 ? 1 : splits;
+        L.cus = cus;
+        const SymShape sh = sym_shape(n, block * ilp, L.jchunk, sym_slots(block, cus));
         L.splits = sh.isplits + 2;
         return L;
     }
@@ -105,6 +109,23 @@ __device__ __forceinline__ float pdiff(float a, float b)
 {
     if (PER) return (float)(int)(__float_as_uint(a) - __float_as_uint(b));
     return a - b;
+}
+
+// FP32 constants of the pair terms, held in VGPRs.  On gfx950 a VALU
+// instruction that reads an SGPR operand issues at half the rate of one that
+// reads VGPRs only (measured: 4.1 vs 2.2 cycles per wave instruction and
+// SIMD), and the compiler keeps wave-uniform values in SGPRs; the empty asm
+// makes the values lane values.  `one` keeps the literal 1.0 out of the
+// coefficient's FMA for the same reason.
+struct VConst {
+    float gamma, m3g, thr2, one;
+};
+
+__device__ __forceinline__ VConst vconst(const PairConst& pc)
+{
+    VConst k{pc.gamma_f, pc.m3gamma_f, pc.thr2_f, 1.0f};
+    asm volatile("" : "+v"(k.gamma), "+v"(k.m3g), "+v"(k.thr2), "+v"(k.one));
+    return k;
 }
 
 // Per-lane state of one particle i.
@@ -228,12 +249,13 @@ __device__ __forceinline__ void near_pair_lds(const LaneF32& L, const float4 pj,
 template <int TENSOR, int ACC, int U, int ILP, bool PER>
 __device__ __forceinline__ void pair_group(LaneF32 (&L)[ILP], const float4 (&pj)[U],
                                            const float4 (&fj)[U], int jg0, int n,
-                                           const PairConst& pc, float gamma, float m3g,
-                                           float thr2, const double* __restrict__ x64,
-                                           double* near_slot, int stride)
+                                           const PairConst& pc, const VConst& kc,
+                                           const double* __restrict__ x64, double* near_slot,
+                                           int stride)
 {
+    const float gamma = kc.gamma, m3g = kc.m3g, thr2 = kc.thr2;
     float dx[ILP][U], dy[ILP][U], dz[ILP][U], r2[ILP][U];
-    float rmin = 3.0e38f;
+    float rmin = 0.0f;
 #pragma unroll
     for (int q = 0; q < ILP; ++q)
 #pragma unroll
@@ -242,7 +264,7 @@ __device__ __forceinline__ void pair_group(LaneF32 (&L)[ILP], const float4 (&pj)
             dy[q][u] = pdiff<PER>(L[q].y, pj[u].y);
             dz[q][u] = pdiff<PER>(L[q].z, pj[u].z);
             r2[q][u] = fmaf(dx[q][u], dx[q][u], fmaf(dy[q][u], dy[q][u], dz[q][u] * dz[q][u]));
-            rmin = fminf(rmin, r2[q][u]);
+            rmin = (q == 0 && u == 0) ? r2[q][u] : fminf(rmin, r2[q][u]);
         }
     if (__builtin_amdgcn_ballot_w64(rmin < thr2) != 0) {
 #pragma unroll
@@ -274,7 +296,7 @@ __device__ __forceinline__ void pair_group(LaneF32 (&L)[ILP], const float4 (&pj)
                     Bt = rinv3;
                 } else {
                     A = fmaf(gamma, rinv3, rinv);
-                    Bt = rinv3 * fmaf(m3g, rinv2, 1.0f);
+                    Bt = rinv3 * fmaf(m3g, rinv2, kc.one);
                 }
                 const float dF = fmaf(dx[q][u], fj[u].x, fmaf(dy[q][u], fj[u].y, dz[q][u] * fj[u].z));
                 const float sB = Bt * dF;
@@ -384,7 +406,7 @@ k_pair_f32_lds(const float4* __restrict__ pos, const float4* __restrict__ frc,
     const int tid = threadIdx.x;
     const int jbeg = s * jchunk;
     const int jend = min(n, jbeg + jchunk);
-    const float gamma = pc.gamma_f, m3g = pc.m3gamma_f, thr2 = pc.thr2_f;
+    const VConst kc = vconst(pc);
     const float4 far_j4 = make_float4(far_j<PER>(), far_j<PER>(), far_j<PER>(), 0.0f);
     const float4 zero4 = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
 
@@ -412,8 +434,8 @@ k_pair_f32_lds(const float4* __restrict__ pos, const float4* __restrict__ frc,
                 pj[u] = s_pos[k + u];
                 fj[u] = s_frc[k + u];
             }
-            pair_group<TENSOR, ACC, GROUP_U, ILP, PER>(L, pj, fj, jt + k, n, pc, gamma, m3g, thr2,
-                                                       x64, near_slot, NS);
+            pair_group<TENSOR, ACC, GROUP_U, ILP, PER>(L, pj, fj, jt + k, n, pc, kc, x64,
+                                                       near_slot, NS);
         }
     }
     lanes_store<ILP>(L, n, s, pc.alpha_sum, near_slot, NS, partial);
@@ -440,6 +462,7 @@ k_pair_f32_smem(const float4* __restrict__ pos, const float4* __restrict__ frc,
     const int jbeg = s * jchunk;
     const int jend = min(n, jbeg + jchunk);
     const float gamma = pc.gamma_f, m3g = pc.m3gamma_f, thr2 = pc.thr2_f;
+    const VConst kc = vconst(pc);
     int j = jbeg;
     for (; j + GROUP_U <= jend; j += GROUP_U) {
         float4 pj[GROUP_U], fj[GROUP_U];
@@ -448,8 +471,8 @@ k_pair_f32_smem(const float4* __restrict__ pos, const float4* __restrict__ frc,
             pj[u] = pos[j + u];
             fj[u] = frc[j + u];
         }
-        pair_group<TENSOR, ACC, GROUP_U, ILP, PER>(L, pj, fj, j, n, pc, gamma, m3g, thr2, x64,
-                                                   near_slot, NS);
+        pair_group<TENSOR, ACC, GROUP_U, ILP, PER>(L, pj, fj, j, n, pc, kc, x64, near_slot,
+                                                   NS);
     }
     for (; j < jend; ++j) {
         const float4 pj = pos[j];
@@ -478,41 +501,77 @@ k_pair_f32_smem(const float4* __restrict__ pos, const float4* __restrict__ frc,
 // pair, as variant 0) by nb extra work-groups dispatched last.
 //
 // Rows of 16 lanes.  Each 16-lane row of a wave holds 16 (ILP 2: 32)
-// particles i, one (two) per lane.  A tile of SYM_TJ particles j is staged in LDS in chunks of 16,
-// each chunk stored twice in a row, so that lane q reads element (q + k) mod
-// 16 of a chunk at the constant offset k.  In step k of a chunk lane q pairs
-// its i with that element; the j-side term goes to the lane that owns the
-// element through a DPP row rotation (row_ror:k: lane m reads lane m - k),
-// so every lane accumulates the j-side sum of one element of the chunk and
-// no cross-lane reduction is needed.  After a chunk each row stores its 16
-// j-side sums in LDS; at the end of a tile the rows are added in a fixed
-// order and written as FP32 j-side partials jpart[c][I][p] (scaled units),
-// which k_fold_sym adds in FP64, in a fixed order, into one more split row.
+// particles i, one (two) per lane.  A tile of SYM_TJ particles j is staged in
+// LDS in chunks of 16, each chunk stored twice in a row, so that lane q reads
+// element (q + k) mod 16 of a chunk at the constant offset k.  In step k of a
+// chunk lane q pairs its i with that element; the j-side term goes to the
+// lane that owns the element through a DPP row rotation (row_ror:k: lane m
+// reads lane m - k), so every lane accumulates the j-side sum of one element
+// of the chunk (16 steps, at most 32 terms, in FP32) and no cross-lane
+// reduction is needed.  After a chunk each row stores its 16 j-side sums in
+// LDS; at the end of a tile the rows are added in FP64 in a fixed order and
+// written as FP32 j-side partials jpart[c][I][p] (scaled units), which
+// k_sym_fold_near adds in FP64, in a fixed order, into one more split row.
+// Tiles are double-buffered: the next tile is read from HBM while the
+// current one is consumed, so a tile costs two barriers.
+//
+// Near pairs.  A pair with r^2 below the near threshold (near contact,
+// overlap, coincident spheres) contributes nothing here, on either side: its
+// r^2 is replaced by +inf, so that rsq gives 0.  The work-group records the
+// block pair (I, J) in a flag matrix instead, and k_sym_fold_near evaluates
+// every pair of the flagged block pairs in FP64, one-sided (both orderings),
+// with the same FP32 threshold test, so that exactly the masked pairs are
+// added back.  The hot loop thus holds no FP64 code and no function call.
 
-constexpr int SYM_TJ = 128;   // j tile: 8 chunks of 16
-
-SymShape sym_shape(int n, int block, int splits)
+// Split schedule.  The i-blocks' virtual j ranges are cut alike, and the
+// launch orders its work-groups diagonal blocks first, then split 0 of every
+// i-block, split 1, ...  The hardware starts work-groups in that order as
+// resident ones finish, so the work-groups that run last are the short ones:
+// a split takes about the share of the remaining range that one round of
+// resident work-groups covers (nb * size / slots of it, at most 1/splits of
+// the whole range, at least one tile), which leaves a tail of about one tile
+// instead of one whole split.
+SymShape sym_shape(int n, int block, int splits, int slots)
 {
     SymShape sh;
     sh.nb = (n + block - 1) / block;
     sh.h = (sh.nb - 1) / 2;
     sh.extra = (sh.nb >= 2 && (sh.nb & 1) == 0) ? 1 : 0;
     sh.lmax = (sh.h + sh.extra) * block;
-    int s = splits < 1 ? 1 : splits;
     const int tiles = sh.lmax / SYM_TJ;
-    if (s > tiles) s = tiles > 0 ? tiles : 1;
-    const int per = (tiles + s - 1) / s;
-    sh.chunk = (per > 0 ? per : 1) * SYM_TJ;
-    sh.isplits = sh.lmax > 0 ? (sh.lmax + sh.chunk - 1) / sh.chunk : 1;
+    const int sp = splits < 1 ? 1 : splits;
+    const int64_t big = std::max<int64_t>(1, (tiles + sp - 1) / sp);
+    const int64_t sl = std::max(1, slots);
+    int k = 0, at = 0;
+    sh.off[0] = 0;
+    while (at < tiles) {
+        const int64_t left = tiles - at;
+        int64_t size = (left * sh.nb + sl - 1) / sl;
+        size = std::min(std::max<int64_t>(size, 1), big);
+        if (k == SYM_MAX_SPLITS - 1) size = left;
+        at += (int)std::min(size, left);
+        sh.off[++k] = at;
+    }
+    if (k == 0) sh.off[++k] = 0;   // one empty split (a single block)
+    sh.isplits = k;
+    for (int m = k + 1; m <= SYM_MAX_SPLITS; ++m) sh.off[m] = at;
     return sh;
+}
+
+int sym_slots(int block, int cus)
+{
+    // LDS per work-group (two staged tiles or one block, the j-side rows)
+    // against 160 KiB per CU, and at most 16 resident waves per CU (four per
+    // SIMD: the register budget of the kernel)
+    const int lds = 2 * 512 * 16 + 3 * (block / 16) * SYM_TJ * 4;
+    const int by_lds = (160 * 1024) / lds;
+    const int by_waves = 16 / (block / 64) > 0 ? 16 / (block / 64) : 1;
+    return std::max(1, std::min(by_lds, by_waves)) * std::max(1, cus);
 }
 
 SymShape sym_shape_of(const PairLaunch& L, int n)
 {
-    SymShape sh = sym_shape(n, L.block * L.ilp, 1);
-    sh.chunk = L.jchunk;
-    sh.isplits = L.splits - 2;
-    return sh;
+    return sym_shape(n, L.block * L.ilp, L.jchunk, sym_slots(L.block, L.cus));
 }
 
 size_t sym_jpart_floats(const SymShape& sh) { return (size_t)3 * sh.nb * (size_t)sh.lmax; }
@@ -521,6 +580,19 @@ size_t sym_jpart_offset(const PairLaunch& L, int64_t n)
 {
     const size_t b = (size_t)L.splits * 3 * (size_t)n * sizeof(double);
     return (b + 255) & ~(size_t)255;
+}
+
+size_t sym_flags_offset(const PairLaunch& L, int64_t n)
+{
+    const size_t b = sym_jpart_offset(L, n) +
+                     sym_jpart_floats(sym_shape_of(L, (int)n)) * sizeof(float);
+    return (b + 255) & ~(size_t)255;
+}
+
+size_t sym_workspace_bytes(const PairLaunch& L, int64_t n)
+{
+    const SymShape sh = sym_shape_of(L, (int)n);
+    return sym_flags_offset(L, n) + (size_t)sh.nb * (size_t)sh.nb * sizeof(uint32_t);
 }
 
 // Compile-time loop: f(integral_constant<int, U>) for U = B .. E-1.
@@ -552,78 +624,100 @@ __device__ __forceinline__ float add_row_rot(float acc, float v)
     }
 }
 
-// One near pair (i, j) of the symmetric kernel in FP64: T(r_ij) F_j is added
-// to the particle's LDS slot (components `stride` apart), T(r_ij) F_i
-// (= T(r_ji) F_i) is added to v*.  Out of line: the rare branch then holds no
-// registers of the hot loop.
-template <int TENSOR, bool PER>
-__device__ __attribute__((noinline)) void sym_near_pair(const LaneF32& L, float fi0, float fi1,
-                                                       float fi2, float4 pj, float4 fj, int jg,
-                                                       const PairConst& pc,
-                                                       const double* __restrict__ x64,
-                                                       double* slot, int stride, double& v0,
-                                                       double& v1, double& v2)
+// Per-lane state of one particle i of the symmetric kernel (FP32 only).
+struct SymLane {
+    float x, y, z;        // position
+    float s0, s1, s2;     // running sums of the i side (scaled units)
+    float c0, c1, c2;     // Kahan compensations
+};
+
+template <int ILP, int BLOCK, bool PER>
+__device__ __forceinline__ void sym_lanes_init(SymLane (&L)[ILP], const float4* __restrict__ pos,
+                                               int n, int ib)
 {
-    double d0, d1, d2;
-    near_diff<PER>(L, pj, jg, pc, x64, d0, d1, d2);
-    double n0 = slot[0], n1 = slot[stride], n2 = slot[2 * stride];
-    near_term<TENSOR>(pc, d0, d1, d2, (double)fj.x, (double)fj.y, (double)fj.z, n0, n1, n2);
-    slot[0] = n0;
-    slot[stride] = n1;
-    slot[2 * stride] = n2;
-    near_term<TENSOR>(pc, d0, d1, d2, (double)fi0, (double)fi1, (double)fi2, v0, v1, v2);
+    const int ibase = ib * (BLOCK * ILP) + (int)threadIdx.x;
+#pragma unroll
+    for (int l = 0; l < ILP; ++l) {
+        const int i = ibase + l * BLOCK;
+        if (i < n) {
+            const float4 p = pos[i];
+            L[l].x = p.x;
+            L[l].y = p.y;
+            L[l].z = p.z;
+        } else {
+            L[l].x = L[l].y = L[l].z = far_i<PER>();
+        }
+        L[l].s0 = L[l].s1 = L[l].s2 = 0.0f;
+        L[l].c0 = L[l].c1 = L[l].c2 = 0.0f;
+    }
+}
+
+// i-side sums of the lane particles -> split row s (FP64, physical units)
+template <int ILP, int BLOCK>
+__device__ __forceinline__ void sym_lanes_store(const SymLane (&L)[ILP], int n, int ib, int s,
+                                                double alpha, double* __restrict__ partial)
+{
+    const int ibase = ib * (BLOCK * ILP) + (int)threadIdx.x;
+#pragma unroll
+    for (int l = 0; l < ILP; ++l) {
+        const int i = ibase + l * BLOCK;
+        if (i < n) {
+            const size_t base = (size_t)s * 3 * (size_t)n + (size_t)i;
+            partial[base] = alpha * ((double)L[l].s0 - (double)L[l].c0);
+            partial[base + (size_t)n] = alpha * ((double)L[l].s1 - (double)L[l].c1);
+            partial[base + 2 * (size_t)n] = alpha * ((double)L[l].s2 - (double)L[l].c2);
+        }
+    }
 }
 
 // Steps K0 .. K0+U-1 of a chunk for one lane and its ILP particles i: pairs
 // (i, element (q + k) mod 16).  sp/sf: this lane's view of the doubled chunk
-// (element (q + k) mod 16 at offset k).  jgc: global index of element 0 of the
-// chunk.  y: the running FP32 sums of the i side (for ACC > 0 the terms since
-// the last compensated add, started from -c; for ACC = 0 the sums themselves);
-// a compensation block of ACC terms may span groups.  aj*: the j-side sums of
-// element q (scaled units), started by step 0.  near_slot: this lane's LDS
-// slot of its first particle (particle l at + l BLOCK, components NS apart).
-template <int TENSOR, int ACC, bool PER, int K0, int U, int ILP, int BLOCK>
-__device__ __forceinline__ void sym_steps(LaneF32 (&L)[ILP], const float (&fi)[ILP][3],
+// (element (q + k) mod 16 at offset k).  y: the running FP32 sums of the i
+// side (for ACC > 0 the terms since the last compensated add, started from
+// -c; for ACC = 0 the sums themselves); a compensation block of ACC terms may
+// span groups.  aj*: the j-side sums of element q (scaled units), started by
+// step 0.  near: set when a pair of the group is below the near threshold
+// (that pair then contributes nothing).
+template <int TENSOR, int ACC, bool PER, int K0, int U, int ILP>
+__device__ __forceinline__ void sym_steps(SymLane (&L)[ILP], const float (&fi)[ILP][3],
                                           float (&y)[ILP][3], float& aj0, float& aj1, float& aj2,
-                                          const float4* sp, const float4* sf, int jgc, int q,
-                                          int n, const PairConst& pc, float gamma, float m3g,
-                                          float thr2, double inv_alpha_sum,
-                                          const double* __restrict__ x64, double* near_slot)
+                                          const float4* sp, const float4* sf,
+                                          const VConst& kc, bool& near)
 {
-    constexpr int NS = BLOCK * ILP;
+    const float gamma = kc.gamma, m3g = kc.m3g, thr2 = kc.thr2;
     constexpr int KB = ACC > 0 ? ACC : 1;
     static_assert(ACC == 0 || KB % U == 0 || U % KB == 0, "compensation blocks and groups");
     // groups are scheduled one after the other: overlapping them would hold
     // two groups of pair data in registers
     __builtin_amdgcn_sched_barrier(0);
-    float4 pj[U], fj[U];
+    float pjx[U], pjy[U], pjz[U], fjx[U], fjy[U], fjz[U];
     float dx[ILP][U], dy[ILP][U], dz[ILP][U], r2[ILP][U];
-    float rmin = 3.0e38f;
+    float rmin = 0.0f;
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-        pj[u] = sp[K0 + u];
-        fj[u] = sf[K0 + u];
+        const float4 p = sp[K0 + u];
+        const float4 f = sf[K0 + u];
+        pjx[u] = p.x;
+        pjy[u] = p.y;
+        pjz[u] = p.z;
+        fjx[u] = f.x;
+        fjy[u] = f.y;
+        fjz[u] = f.z;
 #pragma unroll
         for (int l = 0; l < ILP; ++l) {
-            dx[l][u] = pdiff<PER>(L[l].x, pj[u].x);
-            dy[l][u] = pdiff<PER>(L[l].y, pj[u].y);
-            dz[l][u] = pdiff<PER>(L[l].z, pj[u].z);
+            dx[l][u] = pdiff<PER>(L[l].x, pjx[u]);
+            dy[l][u] = pdiff<PER>(L[l].y, pjy[u]);
+            dz[l][u] = pdiff<PER>(L[l].z, pjz[u]);
             r2[l][u] = fmaf(dx[l][u], dx[l][u], fmaf(dy[l][u], dy[l][u], dz[l][u] * dz[l][u]));
-            rmin = fminf(rmin, r2[l][u]);
+            rmin = (l == 0 && u == 0) ? r2[l][u] : fminf(rmin, r2[l][u]);
         }
     }
-    // near pairs (rare): masked out of the FP32 code here, evaluated in FP64
-    // after it, when this group's FP32 data are no longer live
-    uint32_t nmask = 0;   // bit l U + u
-    if (__builtin_amdgcn_ballot_w64(rmin < thr2) != 0) {
+    if (__builtin_amdgcn_ballot_w64(rmin < thr2) != 0) {   // rare
+        near = true;
 #pragma unroll
         for (int l = 0; l < ILP; ++l)
 #pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const bool nr = r2[l][u] < thr2;
-                nmask |= nr ? (1u << (l * U + u)) : 0u;
-                r2[l][u] = nr ? __builtin_inff() : r2[l][u];
-            }
+            for (int u = 0; u < U; ++u) r2[l][u] = (r2[l][u] < thr2) ? __builtin_inff() : r2[l][u];
     }
     StaticFor<0, U>::run([&](auto u_c) {
         constexpr int u = decltype(u_c)::value;
@@ -648,15 +742,14 @@ __device__ __forceinline__ void sym_steps(LaneF32 (&L)[ILP], const float (&fi)[I
                 Bt = rinv3;
             } else {
                 A = fmaf(gamma, rinv3, rinv);
-                Bt = rinv3 * fmaf(m3g, rinv2, 1.0f);
+                Bt = rinv3 * fmaf(m3g, rinv2, kc.one);
             }
             // i side: T F_j
-            const float dFj =
-                fmaf(dx[l][u], fj[u].x, fmaf(dy[l][u], fj[u].y, dz[l][u] * fj[u].z));
+            const float dFj = fmaf(dx[l][u], fjx[u], fmaf(dy[l][u], fjy[u], dz[l][u] * fjz[u]));
             const float sBj = Bt * dFj;
-            y[l][0] = fmaf(A, fj[u].x, fmaf(sBj, dx[l][u], y[l][0]));
-            y[l][1] = fmaf(A, fj[u].y, fmaf(sBj, dy[l][u], y[l][1]));
-            y[l][2] = fmaf(A, fj[u].z, fmaf(sBj, dz[l][u], y[l][2]));
+            y[l][0] = fmaf(A, fjx[u], fmaf(sBj, dx[l][u], y[l][0]));
+            y[l][1] = fmaf(A, fjy[u], fmaf(sBj, dy[l][u], y[l][1]));
+            y[l][2] = fmaf(A, fjz[u], fmaf(sBj, dz[l][u], y[l][2]));
             // j side: T F_i of this lane's particles, summed before the hand-over
             const float dFi =
                 fmaf(dx[l][u], fi[l][0], fmaf(dy[l][u], fi[l][1], dz[l][u] * fi[l][2]));
@@ -703,90 +796,164 @@ __device__ __forceinline__ void sym_steps(LaneF32 (&L)[ILP], const float (&fi)[I
             }
         }
     });
-    if (__builtin_amdgcn_ballot_w64(nmask != 0) != 0) {
-        // The lane index and the tile pointers pass through an empty asm:
-        // the index arithmetic of this branch is not hoisted into the hot
-        // loop, and the tile is read again here instead of keeping the
-        // group's records live across the FP32 code.
-        int qn = q;
-        const float4* spn = sp;
-        const float4* sfn = sf;
-        asm volatile("" : "+v"(qn), "+v"(spn), "+v"(sfn));
+    // The sums are materialised here: otherwise their addition chains are
+    // sunk towards their only use at the end of the chunk, and the terms of
+    // all steps stay live until then.
+    asm volatile("" : "+v"(aj0), "+v"(aj1), "+v"(aj2));
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-            uint32_t um = 0;
+    for (int l = 0; l < ILP; ++l)
+        asm volatile("" : "+v"(y[l][0]), "+v"(y[l][1]), "+v"(y[l][2]), "+v"(L[l].s0),
+                     "+v"(L[l].s1), "+v"(L[l].s2), "+v"(L[l].c0), "+v"(L[l].c1), "+v"(L[l].c2));
+}
+
+// Diagonal block, one-sided: a group of G particles j (broadcast LDS reads)
+// for every lane particle.  ig: global indices of the lane particles, jg0:
+// global index of the group's first j.  Near pairs are masked as in
+// sym_steps; near is set only for pairs other than a particle with itself.
+// ACC: 0 plain FP32 sums, k >= 1 Kahan compensation once per k terms.
+template <int TENSOR, int ACC, int G, int ILP, bool PER>
+__device__ __forceinline__ void diag_group(SymLane (&L)[ILP], const int (&ig)[ILP],
+                                           const float4* sp, const float4* sf, int jg0,
+                                           const VConst& kc, bool& near)
+{
+    const float gamma = kc.gamma, m3g = kc.m3g, thr2 = kc.thr2;
+    float pjx[G], pjy[G], pjz[G], fjx[G], fjy[G], fjz[G];
+    float dx[ILP][G], dy[ILP][G], dz[ILP][G], r2[ILP][G];
+    float rmin = 0.0f;
 #pragma unroll
-            for (int l = 0; l < ILP; ++l) um |= (nmask >> (l * U + u)) & 1u;
-            if (__builtin_amdgcn_ballot_w64(um != 0) == 0) continue;
-            const int jg = jgc + ((qn + K0 + u) & 15);
-            double v0 = 0.0, v1 = 0.0, v2 = 0.0;
+    for (int u = 0; u < G; ++u) {
+        const float4 p = sp[u];
+        const float4 f = sf[u];
+        pjx[u] = p.x;
+        pjy[u] = p.y;
+        pjz[u] = p.z;
+        fjx[u] = f.x;
+        fjy[u] = f.y;
+        fjz[u] = f.z;
 #pragma unroll
-            for (int l = 0; l < ILP; ++l)
-                if (((nmask >> (l * U + u)) & 1u) && L[l].i < n && jg < n && jg != L[l].i)
-                    sym_near_pair<TENSOR, PER>(L[l], fi[l][0], fi[l][1], fi[l][2], spn[K0 + u],
-                                               sfn[K0 + u], jg, pc, x64, near_slot + l * BLOCK,
-                                               NS, v0, v1, v2);
-            // the owner of element (q + k) mod 16 is lane q + k of the row
-            const int lane = (int)(threadIdx.x & 63);
-            const int src = (lane & ~15) | ((qn - (K0 + u)) & 15);
-            v0 = __shfl(v0, src);
-            v1 = __shfl(v1, src);
-            v2 = __shfl(v2, src);
-            aj0 += (float)(v0 * inv_alpha_sum);
-            aj1 += (float)(v1 * inv_alpha_sum);
-            aj2 += (float)(v2 * inv_alpha_sum);
-            // one near step at a time: keeps the FP64 temporaries of different
-            // steps from being live together
-            __builtin_amdgcn_sched_barrier(0);
+        for (int l = 0; l < ILP; ++l) {
+            dx[l][u] = pdiff<PER>(L[l].x, pjx[u]);
+            dy[l][u] = pdiff<PER>(L[l].y, pjy[u]);
+            dz[l][u] = pdiff<PER>(L[l].z, pjz[u]);
+            r2[l][u] = fmaf(dx[l][u], dx[l][u], fmaf(dy[l][u], dy[l][u], dz[l][u] * dz[l][u]));
+            rmin = (l == 0 && u == 0) ? r2[l][u] : fminf(rmin, r2[l][u]);
+        }
+    }
+    if (__builtin_amdgcn_ballot_w64(rmin < thr2) != 0) {
+        bool other = false;
+#pragma unroll
+        for (int l = 0; l < ILP; ++l)
+#pragma unroll
+            for (int u = 0; u < G; ++u) {
+                const bool nr = r2[l][u] < thr2;
+                other = other || (nr && jg0 + u != ig[l]);
+                r2[l][u] = nr ? __builtin_inff() : r2[l][u];
+            }
+        if (__builtin_amdgcn_ballot_w64(other) != 0) near = true;
+    }
+#pragma unroll
+    for (int l = 0; l < ILP; ++l) {
+        constexpr int KB = ACC > 0 ? ACC : G;
+#pragma unroll
+        for (int u0 = 0; u0 < G; u0 += KB) {
+            float y0 = ACC ? -L[l].c0 : L[l].s0;
+            float y1 = ACC ? -L[l].c1 : L[l].s1;
+            float y2 = ACC ? -L[l].c2 : L[l].s2;
+#pragma unroll
+            for (int u = u0; u < u0 + KB; ++u) {
+                const float rinv = __builtin_amdgcn_rsqf(r2[l][u]);
+                const float rinv2 = rinv * rinv;
+                const float rinv3 = rinv2 * rinv;
+                float A, Bt;
+                if (TENSOR == T_OSEEN) {
+                    A = rinv;
+                    Bt = rinv3;
+                } else {
+                    A = fmaf(gamma, rinv3, rinv);
+                    Bt = rinv3 * fmaf(m3g, rinv2, kc.one);
+                }
+                const float dF = fmaf(dx[l][u], fjx[u], fmaf(dy[l][u], fjy[u], dz[l][u] * fjz[u]));
+                const float sB = Bt * dF;
+                y0 = fmaf(A, fjx[u], fmaf(sB, dx[l][u], y0));
+                y1 = fmaf(A, fjy[u], fmaf(sB, dy[l][u], y1));
+                y2 = fmaf(A, fjz[u], fmaf(sB, dz[l][u], y2));
+            }
+            if (ACC) {
+                const float t0 = L[l].s0 + y0;
+                const float t1 = L[l].s1 + y1;
+                const float t2 = L[l].s2 + y2;
+                L[l].c0 = (t0 - L[l].s0) - y0;
+                L[l].c1 = (t1 - L[l].s1) - y1;
+                L[l].c2 = (t2 - L[l].s2) - y2;
+                L[l].s0 = t0;
+                L[l].s1 = t1;
+                L[l].s2 = t2;
+            } else {
+                L[l].s0 = y0;
+                L[l].s1 = y1;
+                L[l].s2 = y2;
+            }
         }
     }
 }
 
+// Minimum resident waves per SIMD the register allocation must allow: four
+// with work-groups of 256 or 512 lanes (40 / 64 KiB of LDS: four / two
+// work-groups per CU); 128-lane groups (28 KiB) reach at most three.
+template <int BLOCK>
+struct SymWaves {
+    static constexpr int value = BLOCK >= 256 ? 4 : 2;
+};
+
 // ILP particles per lane (ILP 2: the i-block of BLOCK * ILP particles has
 // particle tid and tid + BLOCK in lane tid), groups of U steps.
+// flags: nb x nb block-pair matrix of near pairs (see k_sym_fold_near).
 template <int TENSOR, int ACC, int BLOCK, int ILP, bool PER>
-__global__ void __launch_bounds__(BLOCK, ILP == 2 ? 3 : 1)   // ILP 2: at least 3 waves per SIMD
-k_pair_f32_sym(const float4* __restrict__ pos, const float4* __restrict__ frc,
-               const double* __restrict__ x64, int n, SymShape sh, PairConst pc,
-               double* __restrict__ partial, float* __restrict__ jpart)
+__global__ void __launch_bounds__(BLOCK, SymWaves<BLOCK>::value)
+k_pair_f32_sym(const float4* __restrict__ pos, const float4* __restrict__ frc, int n, SymShape sh,
+               PairConst pc, double* __restrict__ partial, float* __restrict__ jpart,
+               uint32_t* __restrict__ flags)
 {
     constexpr int B = BLOCK * ILP;   // particles per block
-    constexpr int NS = B;            // stride of the near slots
     constexpr int U = ILP == 1 ? 8 : 4;
     static_assert(B % SYM_TJ == 0, "j tiles must not straddle blocks");
     constexpr int ROWS = BLOCK / 16;
-    constexpr int NPOS = B > 2 * SYM_TJ ? B : 2 * SYM_TJ;
-    __shared__ float4 s_pos[NPOS];
-    __shared__ float4 s_frc[NPOS];
-    __shared__ double s_near[3 * B];
+    constexpr int TS = 2 * SYM_TJ;                      // slots of one staged tile
+    constexpr int NSLOT = 2 * TS > B ? 2 * TS : B;      // two tiles, or one diagonal block
+    constexpr int LOADS = (2 * SYM_TJ + BLOCK - 1) / BLOCK;   // tile records per thread
+    __shared__ float4 s_pos[NSLOT];
+    __shared__ float4 s_frc[NSLOT];
     __shared__ float s_jacc[3 * ROWS * SYM_TJ];
     const int tid = threadIdx.x;
-    const int nsym = sh.nb * sh.isplits;
-    const bool diag = (int)blockIdx.x >= nsym;
+    // work-groups: the nb diagonal blocks first, then split-major (see sym_shape)
+    const bool diag = (int)blockIdx.x < sh.nb;
     int ib, s;
     if (diag) {
-        ib = (int)blockIdx.x - nsym;
+        ib = (int)blockIdx.x;
         s = sh.isplits;
     } else {
-        map_block(sh.isplits, ib, s);
+        const int w = (int)blockIdx.x - sh.nb;
+        s = w / sh.nb;
+        ib = w - s * sh.nb;
     }
-    LaneF32 L[ILP];
-    lanes_init<ILP, BLOCK, PER>(L, pos, n, ib);
-    double* near_slot = near_slots_init<ILP, BLOCK>(s_near);
-    const float gamma = pc.gamma_f, m3g = pc.m3gamma_f, thr2 = pc.thr2_f;
+    SymLane L[ILP];
+    sym_lanes_init<ILP, BLOCK, PER>(L, pos, n, ib);
+    const VConst kc = vconst(pc);
     const float4 far_j4 = make_float4(far_j<PER>(), far_j<PER>(), far_j<PER>(), 0.0f);
     const float4 zero4 = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    bool near = false;
 
     if (diag) {
         // the i-block with itself: every ordered pair, one-sided, in groups of
-        // four (compensation at least every four terms; groups of eight here
-        // would raise the register count of the whole kernel)
+        // four (compensation at least every four terms)
         constexpr int ACC_D = ACC > 4 ? 4 : ACC;
-        constexpr int GROUP_U = GroupSize<ACC_D>::value;
+        constexpr int G = 4;
         const int jt = ib * B;
+        int ig[ILP];
 #pragma unroll
         for (int r = 0; r < ILP; ++r) {
             const int t = tid + r * BLOCK;
+            ig[r] = jt + t;
             float4 rp = far_j4, rf = zero4;
             if (jt + t < n) {
                 rp = pos[jt + t];
@@ -797,126 +964,230 @@ k_pair_f32_sym(const float4* __restrict__ pos, const float4* __restrict__ frc,
         }
         __syncthreads();
 #pragma unroll 1
-        for (int k = 0; k < B; k += GROUP_U) {
-            float4 pj[GROUP_U], fj[GROUP_U];
-#pragma unroll
-            for (int u = 0; u < GROUP_U; ++u) {
-                pj[u] = s_pos[k + u];
-                fj[u] = s_frc[k + u];
-            }
-            pair_group<TENSOR, ACC_D, GROUP_U, ILP, PER>(L, pj, fj, jt + k, n, pc, gamma, m3g,
-                                                         thr2, x64, near_slot, NS);
-        }
-        lanes_store<ILP>(L, n, s, pc.alpha_sum, near_slot, NS, partial);
+        for (int k = 0; k < B; k += G)
+            diag_group<TENSOR, ACC_D, G, ILP, PER>(L, ig, s_pos + k, s_frc + k, jt + k, kc, near);
+        if (near && (tid & 63) == 0) flags[(size_t)ib * sh.nb + ib] = 1u;
+        sym_lanes_store<ILP, BLOCK>(L, n, ib, s, pc.alpha_sum, partial);
         return;
     }
 
     float fi[ILP][3];
 #pragma unroll
     for (int l = 0; l < ILP; ++l) {
+        const int i = ib * B + tid + l * BLOCK;
         fi[l][0] = fi[l][1] = fi[l][2] = 0.0f;
-        if (L[l].i < n) {
-            const float4 f = frc[L[l].i];
+        if (i < n) {
+            const float4 f = frc[i];
             fi[l][0] = f.x;
             fi[l][1] = f.y;
             fi[l][2] = f.z;
         }
     }
     float y[ILP][3];
-    const double inv_alpha_sum = 1.0 / pc.alpha_sum;
     const int q = tid & 15;
     const int row = tid >> 4;
     const int half = sh.nb >> 1;
     const int lI = (sh.h + ((sh.extra && ib < half) ? 1 : 0)) * B;
-    const int pbeg = s * sh.chunk;
-    const int pend = min(lI, pbeg + sh.chunk);
-    // first particle of the tile at virtual position pt
-    auto tile_first = [&](int pt) {
-        const int J = (ib + 1 + pt / B) % sh.nb;
-        return J * B + (pt % B);
-    };
-    // Each tile is loaded at its start: a register prefetch of the next tile
-    // would live across the chunk loop, and with two particles per lane it is
-    // spilled (at N = 65536, 170 MiB more HBM writes per launch, for 0.4 % of
-    // time).  The other work-groups on the CU cover the load latency.
-    for (int pt = pbeg; pt < pend; pt += SYM_TJ) {
-        const int jt = tile_first(pt);
-        __syncthreads();
-        if (tid < SYM_TJ) {
-            float4 rp = far_j4, rf = zero4;
-            const int j = jt + tid;
-            if (j < n) {
-                rp = pos[j];
-                rf = frc[j];
-            }
-            const int c = tid >> 4, e = tid & 15;
-            s_pos[c * 32 + e] = rp;
-            s_pos[c * 32 + 16 + e] = rp;
-            s_frc[c * 32 + e] = rf;
-            s_frc[c * 32 + 16 + e] = rf;
+    const int pbeg = sh.off[s] * SYM_TJ;
+    const int pend = min(lI, sh.off[s + 1] * SYM_TJ);
+    // block J and first particle of the tile at virtual position pt
+    auto tile_block = [&](int pt) { return (ib + 1 + pt / B) % sh.nb; };
+    // this thread's records of the tile at pt: element e of record r is
+    // position (r < SYM_TJ) or force of particle jt + (r mod SYM_TJ)
+    auto tile_load = [&](int pt, float4 (&rec)[LOADS]) {
+        const int jt = tile_block(pt) * B + (pt % B);
+#pragma unroll
+        for (int m = 0; m < LOADS; ++m) {
+            const int r = tid + m * BLOCK;
+            const int j = jt + (r & (SYM_TJ - 1));
+            const float4* src = r < SYM_TJ ? pos : frc;
+            const float fill = r < SYM_TJ ? far_j<PER>() : 0.0f;
+            rec[m] = make_float4(fill, fill, fill, 0.0f);
+            if (r < 2 * SYM_TJ && j < n) rec[m] = src[j];
         }
-        __syncthreads();
+    };
+    // chunk c of a tile at slots c * 32 + e and c * 32 + 16 + e
+    auto tile_store = [&](int buf, const float4 (&rec)[LOADS]) {
+#pragma unroll
+        for (int m = 0; m < LOADS; ++m) {
+            const int r = tid + m * BLOCK;
+            if (r < 2 * SYM_TJ) {
+                const int e = r & (SYM_TJ - 1);
+                float4* dst = (r < SYM_TJ ? s_pos : s_frc) + buf * TS + (e >> 4) * 32 + (e & 15);
+                dst[0] = rec[m];
+                dst[16] = rec[m];
+            }
+        }
+    };
+    float4 rec[LOADS];
+    if (pbeg < pend) {
+        tile_load(pbeg, rec);
+        tile_store(0, rec);
+    }
+    // the lane's own records are waited for here, once: a wait inside the
+    // chunk loop would also wait for the next tile's loads in flight
+#pragma unroll
+    for (int l = 0; l < ILP; ++l)
+        asm volatile("" : "+v"(L[l].x), "+v"(L[l].y), "+v"(L[l].z), "+v"(fi[l][0]), "+v"(fi[l][1]),
+                     "+v"(fi[l][2]));
+    __syncthreads();
+#pragma unroll 1
+    for (int pt = pbeg, buf = 0; pt < pend; pt += SYM_TJ, buf ^= 1) {
+        const bool more = pt + SYM_TJ < pend;
+        if (more) tile_load(pt + SYM_TJ, rec);   // consumed after the chunk loop
 #pragma unroll 1
         for (int c = 0; c < SYM_TJ / 16; ++c) {
             float aj0, aj1, aj2;
-            const float4* sp = s_pos + c * 32 + q;
-            const float4* sf = s_frc + c * 32 + q;
-            const int jgc = jt + c * 16;
+            const float4* sp = s_pos + buf * TS + c * 32 + q;
+            const float4* sf = s_frc + buf * TS + c * 32 + q;
             StaticFor<0, 16 / U>::run([&](auto g_c) {
                 constexpr int K0 = decltype(g_c)::value * U;
-                sym_steps<TENSOR, ACC, PER, K0, U, ILP, BLOCK>(L, fi, y, aj0, aj1, aj2, sp, sf,
-                                                               jgc, q, n, pc, gamma, m3g, thr2,
-                                                               inv_alpha_sum, x64, near_slot);
+                sym_steps<TENSOR, ACC, PER, K0, U, ILP>(L, fi, y, aj0, aj1, aj2, sp, sf, kc, near);
             });
             s_jacc[(0 * ROWS + row) * SYM_TJ + c * 16 + q] = aj0;
             s_jacc[(1 * ROWS + row) * SYM_TJ + c * 16 + q] = aj1;
             s_jacc[(2 * ROWS + row) * SYM_TJ + c * 16 + q] = aj2;
         }
-        __syncthreads();
-        if (tid < SYM_TJ) {
-#pragma unroll
-            for (int k = 0; k < 3; ++k) {
-                float sum = 0.0f;
-#pragma unroll
-                for (int r = 0; r < ROWS; ++r) sum += s_jacc[(k * ROWS + r) * SYM_TJ + tid];
-                jpart[((size_t)k * sh.nb + ib) * (size_t)sh.lmax + (size_t)(pt + tid)] = sum;
+        if (more) tile_store(buf ^ 1, rec);
+        if (near) {
+            const int J = tile_block(pt);
+            if ((tid & 63) == 0) {
+                flags[(size_t)ib * sh.nb + J] = 1u;
+                flags[(size_t)J * sh.nb + ib] = 1u;
             }
+            near = false;
         }
+        __syncthreads();   // the tile's j-side sums are complete, the next tile is staged
+        // rows added in FP64, in row order
+        for (int t = tid; t < 3 * SYM_TJ; t += BLOCK) {
+            const int k = t / SYM_TJ, e = t % SYM_TJ;
+            double sum = 0.0;
+#pragma unroll
+            for (int r = 0; r < ROWS; ++r) sum += (double)s_jacc[(k * ROWS + r) * SYM_TJ + e];
+            jpart[((size_t)k * sh.nb + ib) * (size_t)sh.lmax + (size_t)(pt + e)] = (float)sum;
+        }
+        __syncthreads();   // s_jacc is free for the next tile
     }
-    lanes_store<ILP>(L, n, s, pc.alpha_sum, near_slot, NS, partial);
+    sym_lanes_store<ILP, BLOCK>(L, n, ib, s, pc.alpha_sum, partial);
 }
 
-// out[k n + q] = alpha_sum * (sum of the j-side partials of particle q), FP64,
-// in a fixed order (blocks I = J_q - 1, J_q - 2, ..., then the antipode).
-__global__ void __launch_bounds__(256)
-k_fold_sym(const float* __restrict__ jpart, int n, int block, SymShape sh, double alpha_sum,
-           double* __restrict__ out)
+// FP64 difference x_i - x_j of a near pair (i: position xi of the FP32
+// record): from the FP64 positions when given (nearest image in a box), else
+// from the FP32 records (exact difference of floats, or the fixed-point
+// difference times s).
+template <bool PER>
+__device__ __forceinline__ void near_diff_v(float xi, float yi, float zi, int i, float4 pj, int jg,
+                                            const PairConst& pc, const double* __restrict__ x64,
+                                            double& d0, double& d1, double& d2)
 {
-    const int q = blockIdx.x * 256 + threadIdx.x;
-    if (q >= n) return;
-    const int Jq = q / block, o = q - Jq * block;
+    if (x64) {
+        d0 = x64[3 * (size_t)i + 0] - x64[3 * (size_t)jg + 0];
+        d1 = x64[3 * (size_t)i + 1] - x64[3 * (size_t)jg + 1];
+        d2 = x64[3 * (size_t)i + 2] - x64[3 * (size_t)jg + 2];
+        if (PER) nearest_image_d(pc, d0, d1, d2);
+    } else if (PER) {
+        d0 = (double)(int)(__float_as_uint(xi) - __float_as_uint(pj.x)) * pc.s_q;
+        d1 = (double)(int)(__float_as_uint(yi) - __float_as_uint(pj.y)) * pc.s_q;
+        d2 = (double)(int)(__float_as_uint(zi) - __float_as_uint(pj.z)) * pc.s_q;
+    } else {
+        d0 = (double)xi - (double)pj.x;
+        d1 = (double)yi - (double)pj.y;
+        d2 = (double)zi - (double)pj.z;
+    }
+}
+
+// Last split row of variant 2, one work-group of B threads per block J
+// (thread o: particle q = J B + o):
+//  * the j side: the FP32 partials of the blocks I that took block J,
+//    added in FP64 in a fixed order (I = J - 1, J - 2, ..., then the
+//    antipode), times alpha_sum;
+//  * the near pairs: for every block K flagged with J, every pair (q, j in K)
+//    below the FP32 near threshold (the test of the pair kernel, so exactly
+//    the masked pairs), j != q, evaluated in FP64 (near_term), K ascending,
+//    j ascending.  The flags read are cleared for the next product.
+template <int TENSOR, bool PER>
+__global__ void __launch_bounds__(512)
+k_sym_fold_near(const float* __restrict__ jpart, const float4* __restrict__ pos,
+                const float4* __restrict__ frc, const double* __restrict__ x64, int n, int B,
+                SymShape sh, PairConst pc, uint32_t* __restrict__ flags, double* __restrict__ out)
+{
+    __shared__ float4 s_pos[512];
+    __shared__ float4 s_frc[512];
+    __shared__ uint32_t s_fl[512];
+    const int J = blockIdx.x, o = threadIdx.x;
+    const int q = J * B + o;
     const int nb = sh.nb, half = nb >> 1;
     const size_t cs = (size_t)nb * (size_t)sh.lmax;
     double v0 = 0.0, v1 = 0.0, v2 = 0.0;
-    for (int d = 1; d <= sh.h; ++d) {
-        const int I = (Jq - d + nb) % nb;
-        const size_t at = (size_t)I * sh.lmax + (size_t)(d - 1) * block + o;
-        v0 += (double)jpart[at];
-        v1 += (double)jpart[cs + at];
-        v2 += (double)jpart[2 * cs + at];
-    }
-    if (sh.extra) {
-        const int I = (Jq + half) % nb;
-        if (I < half) {
-            const size_t at = (size_t)I * sh.lmax + (size_t)sh.h * block + o;
+    if (q < n) {
+        for (int d = 1; d <= sh.h; ++d) {
+            const int I = (J - d + nb) % nb;
+            const size_t at = (size_t)I * sh.lmax + (size_t)(d - 1) * B + o;
             v0 += (double)jpart[at];
             v1 += (double)jpart[cs + at];
             v2 += (double)jpart[2 * cs + at];
         }
+        if (sh.extra) {
+            const int I = (J + half) % nb;
+            if (I < half) {
+                const size_t at = (size_t)I * sh.lmax + (size_t)sh.h * B + o;
+                v0 += (double)jpart[at];
+                v1 += (double)jpart[cs + at];
+                v2 += (double)jpart[2 * cs + at];
+            }
+        }
     }
-    out[q] = alpha_sum * v0;
-    out[(size_t)n + q] = alpha_sum * v1;
-    out[2 * (size_t)n + q] = alpha_sum * v2;
+    v0 *= pc.alpha_sum;
+    v1 *= pc.alpha_sum;
+    v2 *= pc.alpha_sum;
+    const float thr2 = pc.thr2_f;
+    float xq = far_i<PER>(), yq = far_i<PER>(), zq = far_i<PER>();
+    if (q < n) {
+        const float4 p = pos[q];
+        xq = p.x;
+        yq = p.y;
+        zq = p.z;
+    }
+    for (int K0 = 0; K0 < nb; K0 += B) {
+        __syncthreads();
+        uint32_t f = 0;
+        if (K0 + o < nb) {
+            f = flags[(size_t)J * nb + K0 + o];
+            if (f) flags[(size_t)J * nb + K0 + o] = 0u;
+        }
+        s_fl[o] = f;
+        __syncthreads();
+        const int kend = min(nb - K0, B);
+        for (int kk = 0; kk < kend; ++kk) {
+            if (s_fl[kk] == 0u) continue;
+            const int jt = (K0 + kk) * B;
+            __syncthreads();
+            s_pos[o] = jt + o < n ? pos[jt + o] : make_float4(far_j<PER>(), far_j<PER>(),
+                                                              far_j<PER>(), 0.0f);
+            s_frc[o] = jt + o < n ? frc[jt + o] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+            __syncthreads();
+            for (int e = 0; e < B; ++e) {
+                const float4 pj = s_pos[e];
+                const float dx = pdiff<PER>(xq, pj.x);
+                const float dy = pdiff<PER>(yq, pj.y);
+                const float dz = pdiff<PER>(zq, pj.z);
+                const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+                const int jg = jt + e;
+                if (r2 < thr2 && jg != q && q < n && jg < n) {
+                    const float4 fj = s_frc[e];
+                    double d0, d1, d2;
+                    near_diff_v<PER>(xq, yq, zq, q, pj, jg, pc, x64, d0, d1, d2);
+                    near_term<TENSOR>(pc, d0, d1, d2, (double)fj.x, (double)fj.y, (double)fj.z,
+                                      v0, v1, v2);
+                }
+            }
+        }
+    }
+    if (q < n) {
+        out[q] = v0;
+        out[(size_t)n + q] = v1;
+        out[2 * (size_t)n + q] = v2;
+    }
 }
 
 // ---------------------------------------------------------------- FP64 path
@@ -1051,31 +1322,40 @@ static hipError_t launch_f32_t(const PairLaunch& L, const float4* pos, const flo
 }
 
 template <int TENSOR, int ACC, int BLOCK, int ILP>
-static hipError_t launch_f32_sym(const PairLaunch& L, const float4* pos, const float4* frc,
-                                 const double* x64, int n, const PairConst& pc, double* partial,
-                                 hipStream_t st)
+static hipError_t launch_f32_sym(const PairLaunch& L, const float4* pos, const float4* frc, int n,
+                                 const PairConst& pc, double* partial, hipStream_t st)
 {
     const SymShape sh = sym_shape_of(L, n);
     float* jpart = (float*)((char*)partial + sym_jpart_offset(L, n));
+    uint32_t* flags = (uint32_t*)((char*)partial + sym_flags_offset(L, n));
     dim3 grid(sh.nb * sh.isplits + sh.nb), block(BLOCK);
     if (pc.box > 0.0)
         hipLaunchKernelGGL((k_pair_f32_sym<TENSOR, ACC, BLOCK, ILP, true>), grid, block, 0, st,
-                           pos, frc, x64, n, sh, pc, partial, jpart);
+                           pos, frc, n, sh, pc, partial, jpart, flags);
     else
         hipLaunchKernelGGL((k_pair_f32_sym<TENSOR, ACC, BLOCK, ILP, false>), grid, block, 0, st,
-                           pos, frc, x64, n, sh, pc, partial, jpart);
+                           pos, frc, n, sh, pc, partial, jpart, flags);
     return hipGetLastError();
 }
 
-hipError_t launch_pair_fold(const PairLaunch& L, int n, const PairConst& pc, double* partial,
+hipError_t launch_pair_fold(const PairLaunch& L, int tensor, const float4* pos, const float4* frc,
+                            const double* x64, int n, const PairConst& pc, double* partial,
                             hipStream_t st)
 {
     if (L.variant != 2) return hipSuccess;
     const SymShape sh = sym_shape_of(L, n);
     const float* jpart = (const float*)((const char*)partial + sym_jpart_offset(L, n));
-    hipLaunchKernelGGL(k_fold_sym, dim3((n + 255) / 256), dim3(256), 0, st, jpart, n,
-                       L.block * L.ilp, sh,
-                       pc.alpha_sum, partial + (size_t)(sh.isplits + 1) * 3 * (size_t)n);
+    uint32_t* flags = (uint32_t*)((char*)partial + sym_flags_offset(L, n));
+    double* out = partial + (size_t)(sh.isplits + 1) * 3 * (size_t)n;
+    const int B = L.block * L.ilp;
+    const bool per = pc.box > 0.0;
+#define SD_FOLD(T, P)                                                                              hipLaunchKernelGGL((k_sym_fold_near<T, P>), dim3(sh.nb), dim3(B), 0, st, jpart, pos, frc,                         x64, n, B, sh, pc, flags, out)
+    if (tensor == T_OSEEN) {
+        if (per) SD_FOLD(T_OSEEN, true); else SD_FOLD(T_OSEEN, false);
+    } else {
+        if (per) SD_FOLD(T_RPY, true); else SD_FOLD(T_RPY, false);
+    }
+#undef SD_FOLD
     return hipGetLastError();
 }
 
@@ -1085,26 +1365,28 @@ static hipError_t launch_f32_b(const PairLaunch& L, const float4* pos, const flo
                                hipStream_t st)
 {
     if (L.variant == 2) {
-        if constexpr (ACC == 0 || ACC == 4 || ACC == 8) {
+        if constexpr (ACC == 0 || ACC == 4 || ACC == 8 || ACC == 16) {
             if (L.block == 128 && L.ilp == 1)
-                return launch_f32_sym<TENSOR, ACC, 128, 1>(L, pos, frc, x64, n, pc, partial, st);
+                return launch_f32_sym<TENSOR, ACC, 128, 1>(L, pos, frc, n, pc, partial, st);
             if (L.block == 256 && L.ilp == 1)
-                return launch_f32_sym<TENSOR, ACC, 256, 1>(L, pos, frc, x64, n, pc, partial, st);
+                return launch_f32_sym<TENSOR, ACC, 256, 1>(L, pos, frc, n, pc, partial, st);
             if (L.block == 512 && L.ilp == 1)
-                return launch_f32_sym<TENSOR, ACC, 512, 1>(L, pos, frc, x64, n, pc, partial, st);
+                return launch_f32_sym<TENSOR, ACC, 512, 1>(L, pos, frc, n, pc, partial, st);
             if (L.block == 128 && L.ilp == 2)
-                return launch_f32_sym<TENSOR, ACC, 128, 2>(L, pos, frc, x64, n, pc, partial, st);
+                return launch_f32_sym<TENSOR, ACC, 128, 2>(L, pos, frc, n, pc, partial, st);
             if (L.block == 256 && L.ilp == 2)
-                return launch_f32_sym<TENSOR, ACC, 256, 2>(L, pos, frc, x64, n, pc, partial, st);
+                return launch_f32_sym<TENSOR, ACC, 256, 2>(L, pos, frc, n, pc, partial, st);
         }
         return hipErrorInvalidValue;
     }
+    if constexpr (ACC <= 8) {   // Kahan blocks of 16: variant 2 only
 #define SD_CASE(B, I)                                                                        \
     if (L.block == B && L.ilp == I)                                                          \
         return launch_f32_t<TENSOR, ACC, B, I>(L, pos, frc, x64, n, pc, partial, st);
-    SD_CASE(64, 1) SD_CASE(128, 1) SD_CASE(256, 1)
-    SD_CASE(64, 2) SD_CASE(128, 2) SD_CASE(256, 2)
+        SD_CASE(64, 1) SD_CASE(128, 1) SD_CASE(256, 1)
+        SD_CASE(64, 2) SD_CASE(128, 2) SD_CASE(256, 2)
 #undef SD_CASE
+    }
     return hipErrorInvalidValue;
 }
 
@@ -1119,6 +1401,7 @@ hipError_t launch_pair_f32(const PairLaunch& L, int tensor, int acc, const float
     case 2: return launch_f32_b<T, 2>(L, pos, frc, x64, n, pc, partial, st);         \
     case 4: return launch_f32_b<T, 4>(L, pos, frc, x64, n, pc, partial, st);         \
     case 8: return launch_f32_b<T, 8>(L, pos, frc, x64, n, pc, partial, st);         \
+    case 16: return launch_f32_b<T, 16>(L, pos, frc, x64, n, pc, partial, st);       \
     default: return hipErrorInvalidValue;                                            \
     }
     if (tensor == T_OSEEN) { SD_ACC(T_OSEEN) }

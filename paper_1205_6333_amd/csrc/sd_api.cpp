@@ -127,31 +127,39 @@ struct Buffer {
 
 struct Workspace {
     Buffer slot[WS_COUNT];
+    // buffers replaced by larger ones: work already enqueued may still use
+    // them, so they are freed only by sd_release (which waits for the device)
+    std::vector<void*> retired;
 };
 static std::map<int, Workspace> g_ws;
 
 // Returns a device buffer of at least `bytes` for workspace slot `which` on the
-// current device (grow-only; growing waits for the device to go idle).
+// current device (grow-only, by at least 1.5x; a new buffer is zeroed).  The
+// buffer it replaces stays allocated until sd_release, so growing never waits
+// for the device.
 sd_status ws_get(int which, size_t bytes, void** out)
 {
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) return fail(SD_EDEVICE, "hipGetDevice failed");
     std::lock_guard<std::mutex> lk(g_mu);
-    Buffer& b = g_ws[dev].slot[which];
+    Workspace& w = g_ws[dev];
+    Buffer& b = w.slot[which];
     if (b.bytes < bytes) {
-        if (b.ptr) {
-            (void)hipDeviceSynchronize();
-            (void)hipFree(b.ptr);
-            b.ptr = nullptr;
-            b.bytes = 0;
-        }
         size_t want = std::max(bytes, (size_t)4096);
+        if (b.bytes) want = std::max(want, b.bytes + b.bytes / 2);
         want = (want + 4095) & ~(size_t)4095;
-        if (hipMalloc(&b.ptr, want) != hipSuccess) {
+        void* p = nullptr;
+        if (hipMalloc(&p, want) != hipSuccess) {
             (void)hipGetLastError();
-            b.ptr = nullptr;
             return fail(SD_ENOMEM, "workspace allocation of %zu bytes failed", want);
         }
+        if (hipMemset(p, 0, want) != hipSuccess) {
+            (void)hipGetLastError();
+            (void)hipFree(p);
+            return fail(SD_EDEVICE, "workspace initialisation failed");
+        }
+        if (b.ptr) w.retired.push_back(b.ptr);
+        b.ptr = p;
         b.bytes = want;
     }
     *out = b.ptr;
@@ -172,6 +180,8 @@ static sd_status ws_release_all()
                 b.ptr = nullptr;
                 b.bytes = 0;
             }
+        for (void* r : kv.second.retired) (void)hipFree(r);
+        kv.second.retired.clear();
     }
     (void)hipSetDevice(cur);
     return SD_OK;
@@ -197,7 +207,7 @@ static int size_class(int64_t n)
 bool sym_fits(int64_t n, int block)
 {
     if (n > INT32_MAX) return false;
-    const SymShape sh = sym_shape((int)n, block, 1);
+    const SymShape sh = sym_shape((int)n, block, 1, 1);
     return sym_jpart_floats(sh) * sizeof(float) <= SYM_WORKSPACE_CAP;
 }
 
@@ -246,15 +256,24 @@ sd_kernel_config choose_config(int32_t prec, int64_t n)
     {
         std::lock_guard<std::mutex> lk(g_mu);
         const ConfigTable& t = g_cfg[prec];
-        if (t.forced) return t.forced_cfg;
-        auto it = t.tuned.find(size_class(n));
-        if (it != t.tuned.end()) {
-            sd_kernel_config c = it->second;
-            // keep the split count proportional to the size class
-            const int64_t tiles = (n + c.block - 1) / c.block;
-            if (c.splits > tiles) c.splits = (int32_t)tiles;
-            return c;
+        sd_kernel_config c{};
+        bool have = false;
+        if (t.forced) {
+            c = t.forced_cfg;
+            have = true;
+        } else {
+            auto it = t.tuned.find(size_class(n));
+            if (it != t.tuned.end()) {
+                c = it->second;
+                // keep the split count proportional to the size class
+                const int64_t tiles = (n + c.block - 1) / c.block;
+                if (c.splits > tiles) c.splits = (int32_t)tiles;
+                have = true;
+            }
         }
+        // a forced or tuned variant-2 shape whose j-side workspace for this n
+        // exceeds the cap falls back to the automatic configuration
+        if (have && !(c.variant == 2 && !sym_fits(n, c.block * c.ilp))) return c;
     }
     return default_config(prec, n);
 }
@@ -279,8 +298,8 @@ sd_status check_config(int32_t prec, const sd_kernel_config& c)
         if (c.block != 128 && c.block != 256 && c.block != 512)
             return fail(SD_EINVAL, "variant 2 needs block 128, 256 or 512");
         if (c.block * c.ilp > 512) return fail(SD_EINVAL, "variant 2 needs block * ilp <= 512");
-        if (c.kahan_block != 0 && c.kahan_block != 4 && c.kahan_block != 8)
-            return fail(SD_EINVAL, "variant 2 needs kahan_block 0, 4 or 8");
+        if (c.kahan_block != 0 && c.kahan_block != 4 && c.kahan_block != 8 && c.kahan_block != 16)
+            return fail(SD_EINVAL, "variant 2 needs kahan_block 0, 4, 8 or 16");
     }
     if (prec == SD_FP64) {
         if (c.variant != 0 || c.ilp != 1)
@@ -288,8 +307,9 @@ sd_status check_config(int32_t prec, const sd_kernel_config& c)
     } else if (prec == SD_FP32_PLAIN) {
         if (c.kahan_block != 0) return fail(SD_EINVAL, "kahan_block must be 0 for SD_FP32_PLAIN");
     } else if (c.kahan_block != 1 && c.kahan_block != 2 && c.kahan_block != 4 &&
-               c.kahan_block != 8) {
-        return fail(SD_EINVAL, "kahan_block must be 1, 2, 4 or 8 for SD_FP32_KAHAN");
+               c.kahan_block != 8 && !(c.variant == 2 && c.kahan_block == 16)) {
+        return fail(SD_EINVAL, "kahan_block must be 1, 2, 4 or 8 (16 with variant 2) for "
+                               "SD_FP32_KAHAN");
     }
     return SD_OK;
 }
@@ -352,7 +372,9 @@ sd_status run_pair(const sd_params* p, int64_t n, const void* pos, const void* f
         e = launch_pair_f32(L, p->tensor, L.acc, (const float4*)pos, (const float4*)frc, x64,
                             (int)n, pc, partial, st);
     prof_end(st, ev);
-    if (e == hipSuccess && prec != SD_FP64) e = launch_pair_fold(L, (int)n, pc, partial, st);
+    if (e == hipSuccess && prec != SD_FP64)
+        e = launch_pair_fold(L, p->tensor, (const float4*)pos, (const float4*)frc, x64, (int)n, pc,
+                             partial, st);
     if (e != hipSuccess) return fail(SD_EDEVICE, "pair kernel launch: %s", hipGetErrorString(e));
     return SD_OK;
 }
@@ -360,7 +382,7 @@ sd_status run_pair(const sd_params* p, int64_t n, const void* pos, const void* f
 PairLaunch plan_pair(int32_t prec, int64_t n)
 {
     const sd_kernel_config c = choose_config(prec, n);
-    PairLaunch L = shape_pair_launch((int)n, c.variant, c.block, c.splits, c.ilp);
+    PairLaunch L = shape_pair_launch((int)n, c.variant, c.block, c.splits, c.ilp, device_cus());
     L.acc = (prec == SD_FP64) ? 0 : c.kahan_block;
     if (prec == SD_FP32_PLAIN) L.acc = 0;
     return L;
@@ -368,8 +390,7 @@ PairLaunch plan_pair(int32_t prec, int64_t n)
 
 size_t partial_bytes(const PairLaunch& L, int64_t n)
 {
-    if (L.variant == 2)
-        return sym_jpart_offset(L, n) + sym_jpart_floats(sym_shape_of(L, (int)n)) * sizeof(float);
+    if (L.variant == 2) return sym_workspace_bytes(L, n);
     return (size_t)L.splits * 3 * (size_t)n * sizeof(double);
 }
 

@@ -67,30 +67,48 @@ PairConst make_pair_const(double a, double eta, int tensor, int overlap, double 
 struct PairLaunch {
     int variant;   // 0 LDS tiles, 1 scalar-cache j stream, 2 pair symmetry (FP32 only)
     int block;     // threads per work-group
-    int splits;    // number of j-range splits actually launched
-    int jchunk;    // particles j per split (multiple of block)
+    int splits;    // number of partial rows written (variants 0/1: j-range splits)
+    int jchunk;    // variants 0/1: particles j per split (multiple of block);
+                   // variant 2: the requested split count the schedule was cut from
     int ilp;       // i per lane
     int acc;       // FP32 accumulation: 0 plain, k = Kahan per k terms
+    int cus;       // variant 2: compute units the schedule was cut for
 };
 
-// Shape the launch for n particles from a requested configuration.
-PairLaunch shape_pair_launch(int n, int variant, int block, int splits, int ilp);
+// Shape the launch for n particles from a requested configuration on a device
+// with `cus` compute units.
+PairLaunch shape_pair_launch(int n, int variant, int block, int splits, int ilp, int cus);
 
 // Block schedule of variant 2 (each pair of distinct blocks once, see
 // k_pair_f32_sym): nb blocks of `block` particles; i-block I takes the h
 // blocks after it (mod nb) and, when nb is even (extra = 1), block I + nb/2
-// if I < nb/2; that virtual j range (at most lmax positions) is cut into
-// isplits splits of chunk positions.  Partial rows: isplits symmetric
-// splits, one row of the one-sided diagonal blocks, one row of the folded j
-// side, so PairLaunch.splits = isplits + 2.  After the rows (256-byte
-// aligned) the workspace holds the FP32 j-side partials, 3 * nb * lmax floats.
+// if I < nb/2; that virtual j range (at most lmax positions, lmax / SYM_TJ
+// tiles) is cut into isplits splits, split k covering tiles
+// [off[k], off[k+1]).  The splits shrink towards the end (see sym_shape), so
+// that the last work-groups of a launch are short.  Partial rows: isplits
+// symmetric splits, one row of the one-sided diagonal blocks, one row of the
+// folded j side and the near pairs, so PairLaunch.splits = isplits + 2.
+// After the rows (256-byte aligned) the workspace holds the FP32 j-side
+// partials, 3 * nb * lmax floats, then (256-byte aligned) the nb x nb
+// near-pair flags (uint32, cleared by the fold kernel after use; a stale
+// nonzero flag costs one extra FP64 pass over that block pair, never a wrong
+// result).
+constexpr int SYM_TJ = 128;          // j tile of the symmetric kernel
+constexpr int SYM_MAX_SPLITS = 96;
 struct SymShape {
-    int nb, h, extra, lmax, chunk, isplits;
+    int nb, h, extra, lmax, isplits;
+    int off[SYM_MAX_SPLITS + 1];
 };
-SymShape sym_shape(int n, int block, int splits);
+// splits: the largest split covers about 1/splits of the range; slots:
+// work-groups resident on the device at once.
+SymShape sym_shape(int n, int block, int splits, int slots);
+// resident work-groups of the symmetric kernel with `block` lanes on `cus` CUs
+int sym_slots(int block, int cus);
 SymShape sym_shape_of(const PairLaunch& L, int n);
 size_t sym_jpart_floats(const SymShape& sh);
 size_t sym_jpart_offset(const PairLaunch& L, int64_t n);
+size_t sym_flags_offset(const PairLaunch& L, int64_t n);
+size_t sym_workspace_bytes(const PairLaunch& L, int64_t n);
 
 // Pair kernels: partial[(s*3 + k)*n + i] = sum over split s of the pair terms
 // (self excluded), FP64 output.
@@ -102,10 +120,12 @@ hipError_t launch_pair_f32(const PairLaunch& L, int tensor, int acc, const float
                            double* partial, hipStream_t st);
 hipError_t launch_pair_f64(const PairLaunch& L, int tensor, const double4* pos, const double4* frc,
                            int n, const PairConst& pc, double* partial, hipStream_t st);
-// Variant 2 only (a no-op otherwise): adds the j-side partials the pair kernel
-// left in the workspace into the last partial row.  Enqueue after the pair
-// kernel, before anything reads the partial rows.
-hipError_t launch_pair_fold(const PairLaunch& L, int n, const PairConst& pc, double* partial,
+// Variant 2 only (a no-op otherwise): the last partial row, from the j-side
+// partials and the near-pair flags the pair kernel left in the workspace.
+// pos/frc: the records the pair kernel read; x64 as for launch_pair_f32.
+// Enqueue after the pair kernel, before anything reads the partial rows.
+hipError_t launch_pair_fold(const PairLaunch& L, int tensor, const float4* pos, const float4* frc,
+                            const double* x64, int n, const PairConst& pc, double* partial,
                             hipStream_t st);
 
 // v_i = mu0 F_i + sum_s partial_s (fixed order).
