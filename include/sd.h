@@ -117,6 +117,26 @@ sd_status mobility_apply(const sd_params* p, int64_t n, const void* pos, const v
                          double* vel, int32_t precision, void* stream);
 
 /*
+ * mobility_apply_noalloc -- mobility_apply for callers that cannot allocate
+ * device memory: code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc.  Same arguments, layouts, checks and
+ * results (to the accuracy of the precision; it always runs the one-sided
+ * kernel, variant 0) as mobility_apply, but it calls no hipMalloc, hipFree or
+ * allocating library routine: its j-split partials (and, in a periodic box,
+ * the fixed-point position records) live in a static device array of
+ * SD_NOALLOC_SCRATCH_BYTES (32 MiB) per device, held from the library's load
+ * until the process ends.  n is limited to what the array holds: 24 n bytes
+ * (40 n in a periodic box with an FP32 precision), i.e. n <= 1398101
+ * (838860); larger n returns SD_EINVAL.  Every call on a device shares that
+ * device's array: calls that overlap on one device (other streams, other
+ * threads) race, and the caller must order them.
+ */
+#define SD_NOALLOC_SCRATCH_BYTES (32u << 20)
+sd_status mobility_apply_noalloc(const sd_params* p, int64_t n, const void* pos,
+                                 const void* force, double* vel, int32_t precision,
+                                 void* stream);
+
+/*
  * mobility_adjoint -- reverse-mode derivative of the product.  For a
  * cotangent lam (dL/dv):
  *   grad_pos   f64[3n], written: d/dx [lam . M(x) F]

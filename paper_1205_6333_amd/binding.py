@@ -83,6 +83,7 @@ def lib() -> ctypes.CDLL:
                                ctypes.c_double)
         sig = {
             "mobility_apply": [P, i64, vp, vp, dp, i32, vp],
+            "mobility_apply_noalloc": [P, i64, vp, vp, dp, i32, vp],
             "mobility_adjoint": [P, i64, vp, vp, vp, dp, dp, i32, vp],
             "sd_step": [P, i64, dp, vp, dp, dp, d, i64, i32, i32, vp],
             "sd_run": [P, i64, dp, vp, dp, d, i64, i64, i32, i32, dp, i64, vp],
@@ -198,6 +199,23 @@ def mobility_apply(pos, force, vel=None, *, params: SdParams = None, precision: 
     p = params if params is not None else globals()["params"]()
     check(lib().mobility_apply(ctypes.byref(p), n, _ptr(pos), _ptr(force), _ptr(vel), prec,
                                _stream(stream)))
+    return vel
+
+
+def mobility_apply_noalloc(pos, force, vel, *, params: SdParams = None, precision: int = None,
+                           stream=None):
+    """v = M(x) F into the caller's vel (n, 3) float64, through the entry point
+    that allocates no device memory (its scratch is a static device array)."""
+    prec = _default_precision(pos) if precision is None else int(precision)
+    _vec4(pos, prec, "pos")
+    _vec4(force, prec, "force")
+    n = pos.shape[0]
+    if force.shape[0] != n:
+        raise ValueError("pos and force differ in length")
+    _vec3(vel, n, "vel")
+    p = params if params is not None else globals()["params"]()
+    check(lib().mobility_apply_noalloc(ctypes.byref(p), n, _ptr(pos), _ptr(force), _ptr(vel),
+                                       prec, _stream(stream)))
     return vel
 
 
