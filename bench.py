@@ -52,15 +52,20 @@ import time
 
 import numpy as np
 
-FLOP_PER_PAIR = 35          # canonical useful flops per pair, see the design doc
+# Useful flops of one ordered pair (FMA = 2, rsqrt = 1): d 3, r^2 5, rsqrt 1,
+# r^-2 1, A 3, B 4, d.F 5, s = B (d.F) 1, A F + s d accumulated 12 (Eq. 7b).
+FLOP_PER_PAIR = 35
 PEAK_FP32_TFLOPS = 157.3    # MI355X published FP32 vector peak
 METRIC = "G pair-interactions/s of RPY mobility product at N=65536 (FP32-comp vs FP64)"
+SMALL_N = 16384             # the second size of the single-product benchmark
 
 # HBM traffic of one product-kernel launch from two rocprofv3 counter passes
 # (FETCH_SIZE, WRITE_SIZE; profiles/pair_kernel_f32_n65536_hbm_counters.md), each
 # scaled by what the counter reads for a plain 256 MiB copy (fetch x 2.00,
-# write x 1.00).  Valid only for the kernel source (SHA-1 of mobility.hip) and
-# launch configuration the counters were taken with; otherwise reported as null.
+# write x 1.00).  Valid only for the kernel sources (SHA-1 of mobility.hip
+# followed by sym_chunk_asm.h) and launch configuration the counters were taken
+# with; otherwise reported as null.
+KERNEL_SOURCES = ("mobility.hip", "sym_chunk_asm.h")
 PMC_TRAFFIC = {"source_sha1": "3202888228eef94652fcc564b6e71d2ab495a07e",
                "n": 65536,
                "config": {"variant": 2, "block": 256, "splits": 32, "ilp": 2, "kahan_block": 8},
@@ -70,12 +75,14 @@ PMC_TRAFFIC = {"source_sha1": "3202888228eef94652fcc564b6e71d2ab495a07e",
 def _measured_traffic(n, cfg):
     """HBM bytes per product-kernel launch, or None if the counters are stale."""
     import hashlib
-    src = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_1205_6333_amd", "csrc",
-                       "mobility.hip")
+    csrc = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_1205_6333_amd", "csrc")
+    h = hashlib.sha1()
     try:
-        sha = hashlib.sha1(open(src, "rb").read()).hexdigest()
+        for name in KERNEL_SOURCES:
+            h.update(open(os.path.join(csrc, name), "rb").read())
     except OSError:
         return None
+    sha = h.hexdigest()
     m = PMC_TRAFFIC
     if sha != m["source_sha1"] or n != m["n"] or dict(cfg) != m["config"]:
         return None
@@ -109,12 +116,27 @@ def _to4(v, dtype, device):
     return torch.tensor(out, dtype=dtype, device=device)
 
 
-def _time_path(sd, pos, frc, vel, prec, steps, warmup):
-    """Warm up, then time `steps` products; returns (wall s, pair-kernel ms avg,
-    event ms total)."""
+def _prewarm(sd, pos, frc, vel, prec, warmup, seconds):
+    """`warmup` untimed products, then more until `seconds` of wall time have
+    passed: the clock of an idle GPU ramps up over its first few hundred ms of
+    load, and the timed region should see the clock of a loaded GPU.  Returns
+    the number of untimed products run."""
     import torch
-    for _ in range(warmup):
-        sd.mobility_apply(pos, frc, vel, precision=prec)
+    done = 0
+    t0 = time.perf_counter()
+    while done < warmup or time.perf_counter() - t0 < seconds:
+        for _ in range(5):
+            sd.mobility_apply(pos, frc, vel, precision=prec)
+        done += 5
+        torch.cuda.synchronize()
+    return done
+
+
+def _time_path(sd, pos, frc, vel, prec, steps, warmup, prewarm_s=0.0):
+    """Warm up, then time `steps` products; returns (wall s, pair-kernel ms avg,
+    event ms total, pair-kernel ms per launch, untimed products)."""
+    import torch
+    untimed = _prewarm(sd, pos, frc, vel, prec, warmup, prewarm_s)
     torch.cuda.synchronize()
     sd.sd_profile_reset()
     sd.sd_profile_enable(True)
@@ -130,7 +152,36 @@ def _time_path(sd, pos, frc, vel, prec, steps, warmup):
     t1 = time.perf_counter()
     sd.sd_profile_enable(False)
     launches, kern_ms = sd.sd_profile_read()
-    return t1 - t0, kern_ms / max(1, launches), ev0.elapsed_time(ev1)
+    per = sd.sd_profile_times()
+    return t1 - t0, kern_ms / max(1, launches), ev0.elapsed_time(ev1), per, untimed
+
+
+def _kernel_name(cfg):
+    if cfg.get("variant") == 2:
+        return "k_pair_f32_sym_asm" if cfg.get("kahan_block") in (16, 32) else "k_pair_f32_sym"
+    return "k_pair_f32_lds" if cfg.get("variant") == 0 else "k_pair_f32_smem"
+
+
+def _small_product(sd, W, dev, args):
+    """The product at N = SMALL_N (same recipe, seeds 1 and 2): wall-clock
+    rate, median pair-kernel launch and its fraction of the FP32 peak."""
+    import torch
+    n = SMALL_N
+    x = W.random_suspension(n, phi=0.05, seed=1)
+    f = W.gaussian_forces(n, seed=2)
+    pos, frc = _to4(x, torch.float32, dev), _to4(f, torch.float32, dev)
+    vel = torch.empty((n, 3), dtype=torch.float64, device=dev)
+    cfg = sd.sd_get_kernel_config(sd.SD_FP32_KAHAN, n)
+    steps = max(20, args.steps)
+    print("bench: timing fp32-kahan n=%d %s" % (n, cfg), file=sys.stderr, flush=True)
+    wall, kern_ms, _, per, _ = _time_path(sd, pos, frc, vel, sd.SD_FP32_KAHAN, steps, 20,
+                                          min(args.prewarm_s, 0.5))
+    pairs = float(n) * n
+    med = float(np.median(per)) if per else kern_ms
+    return {"value": pairs * steps / wall / 1e9, "unit": "G pair-interactions/s",
+            "steps": steps, "ms_per_step": wall * 1e3 / steps, "pair_kernel_ms": kern_ms,
+            "pair_kernel_ms_median": med, "kernel": cfg, "kernel_name": _kernel_name(cfg),
+            "frac_median": FLOP_PER_PAIR * pairs / (med * 1e-3) / 1e12 / PEAK_FP32_TFLOPS}
 
 
 def cpu_baseline(x32, f32, vgpu, n, target_s):
@@ -553,6 +604,10 @@ def main():
                     help="target duration of the oracle CPU-baseline sample")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 GPU path")
+    ap.add_argument("--no-small", action="store_true",
+                    help="skip the N = %d product timed beside the headline size" % SMALL_N)
+    ap.add_argument("--prewarm-s", type=float, default=1.0,
+                    help="untimed products continue until this many seconds have passed")
     ap.add_argument("--tune", action="store_true", help="autotune the kernel shape first (untimed)")
     ap.add_argument("--workload", default="product",
                     choices=["product", "timeloop", "batched", "adjoint", "lubrication", "fcc",
@@ -564,7 +619,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the product is not sharded across GPUs in this "
-              "build (see DESIGN.md for how it would shard); use --gpus 1", file=sys.stderr)
+              "build; use --gpus 1", file=sys.stderr)
         return 2
 
     import torch
@@ -594,8 +649,8 @@ def main():
         tune_report = sd.sd_autotune(n, precision=sd.SD_FP32_KAHAN)
     cfg = sd.sd_get_kernel_config(sd.SD_FP32_KAHAN, n)
     print("bench: timing fp32-kahan %s" % cfg, file=sys.stderr, flush=True)
-    wall, kern_ms, ev_ms = _time_path(sd, pos32, frc32, vel, sd.SD_FP32_KAHAN, args.steps,
-                                      args.warmup)
+    wall, kern_ms, ev_ms, per, untimed = _time_path(sd, pos32, frc32, vel, sd.SD_FP32_KAHAN,
+                                                    args.steps, args.warmup, args.prewarm_s)
     v32 = vel.cpu().numpy()
     pairs = float(n) * n
     value = pairs * args.steps / wall / 1e9
@@ -609,15 +664,18 @@ def main():
                                "N(0,1) (seed 2), FP32 evaluation + Kahan accumulation" % n,
                    "n": n, "precision": "fp32_kahan", "kernel": cfg},
         "event_ms_per_step": ev_ms / args.steps,
+        "untimed_products": untimed,
         "pair_kernel_ms": kern_ms,
+        "pair_kernel_ms_median": float(np.median(per)) if per else None,
+        "pair_kernel_launches": len(per),
+        "value_kernel_median": pairs / (float(np.median(per)) * 1e-3) / 1e9 if per else None,
     }
     achieved = FLOP_PER_PAIR * pairs / (kern_ms * 1e-3) / 1e12
     out["roofline"] = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS,
                        "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_TFLOPS,
                        "traffic": _measured_traffic(n, cfg),
                        "flop_per_pair": FLOP_PER_PAIR,
-                       "kernel": "pair kernel (%s)" % ("k_pair_f32_sym" if cfg.get("variant") == 2
-                                                      else "k_pair_f32_lds/smem")}
+                       "kernel": "pair kernel (%s)" % _kernel_name(cfg)}
     valu = _measured_valu(n, cfg)
     if valu is not None:
         instr, flops = valu
@@ -630,13 +688,15 @@ def main():
         vel64 = torch.empty((n, 3), dtype=torch.float64, device=dev)
         steps64 = max(3, args.steps // 4)
         print("bench: timing fp64", file=sys.stderr, flush=True)
-        wall64, kern64, _ = _time_path(sd, pos64, frc64, vel64, sd.SD_FP64, steps64,
+        wall64, kern64, _, _, _ = _time_path(sd, pos64, frc64, vel64, sd.SD_FP64, steps64,
                                        min(args.warmup, 2))
         out["fp64_value"] = pairs * steps64 / wall64 / 1e9
         out["fp64_pair_kernel_ms"] = kern64
         out["speedup_vs_fp64"] = value / out["fp64_value"]
         v64 = vel64.cpu().numpy()
         out["fp32_vs_fp64_rel2"] = float(np.linalg.norm(v32 - v64) / np.linalg.norm(v64))
+    if not args.no_small and n != SMALL_N:
+        out["n%d" % SMALL_N] = _small_product(sd, W, dev, args)
     if not args.no_cpu:
         print("bench: oracle cpu baseline", file=sys.stderr, flush=True)
         base, err = cpu_baseline(W.round_to_f32(x), W.round_to_f32(f), v32, n, args.cpu_seconds)

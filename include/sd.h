@@ -407,18 +407,25 @@ typedef struct sd_kernel_config {
                              only): every pair of particles in different
                              blocks evaluated once, T(r_ij) F_i handed to j
                              (block symmetry of M, Sec. 3.3); block * ilp
-                             <= 512, kahan_block 0, 4 or 8; library
+                             <= 512, kahan_block 0, 4, 8, or 16 or 32
+                             with block 256 and ilp 2 (those two run the
+                             chunk loop in generated assembly); library
                              workspace of about 6 n^2 / (block * ilp)
                              bytes.  The automatic choice takes it from
-                             n = 32768 on (block 256, ilp 2) while that
-                             workspace stays within 1 GiB */
+                             n = 32768 on (block 256, ilp 2, kahan_block
+                             32 for SD_FP32_KAHAN) while that workspace
+                             stays within 1 GiB */
     int32_t block;        /* work-group size (64, 128 or 256; variant 2: 128,
                              256 or 512) */
     int32_t splits;       /* j-range splits (>= 1): extra work-groups per i-block */
     int32_t ilp;          /* particles i per lane (1 or 2) */
     int32_t kahan_block;  /* SD_FP32_KAHAN: pair terms summed in FP32 before each
                              compensated add (1 = per term, 2, 4, or 8 with
-                             block >= 128); 0 for the other precisions */
+                             block >= 128; variant 2 also 16 or 32); 0 for
+                             the other precisions.  Variant 2 sums the
+                             j side in FP32 over at most 32 terms per
+                             chunk before its FP64 fold, whatever the
+                             value */
 } sd_kernel_config;
 
 /* Force a configuration for a precision (NULL restores automatic choice). */
@@ -444,6 +451,11 @@ sd_status sd_profile_enable(int32_t on);
  * the recorded events). */
 sd_status sd_profile_read(int64_t* launches, double* total_ms);
 sd_status sd_profile_reset(void);
+/* Per-launch pair-kernel times (ms) since the last reset, in launch order: the
+ * first min(cap, count) are written to ms (host buffer of cap floats, may be
+ * NULL when cap is 0); *count (may be NULL) receives how many are held (at
+ * most 65536 after a reset).  Waits for the recorded events. */
+sd_status sd_profile_times(float* ms, int64_t cap, int64_t* count);
 
 /* -------------------------------------------------------------- observables */
 

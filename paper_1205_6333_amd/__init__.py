@@ -11,7 +11,8 @@ from .binding import (SD_AB2, SD_EULER, SD_FP32_KAHAN, SD_FP32_PLAIN, SD_FP64, S
                       mobility_adjoint, mobility_apply, mobility_apply_batched,
                       mobility_apply_noalloc, params,
                       sd_autotune, sd_get_kernel_config, sd_profile_enable, sd_profile_read,
-                      sd_profile_reset, sd_release, sd_run, sd_run_adjoint, sd_run_batched,
+                      sd_profile_reset, sd_profile_times, sd_release, sd_run, sd_run_adjoint,
+                      sd_run_batched,
                       sd_set_kernel_config, sd_step, sd_version)
 from .binding import lub, lubrication_forces, sd_mean_vector, sd_pack, sd_run_lub  # noqa: E402,F401
 from . import autograd  # noqa: E402,F401

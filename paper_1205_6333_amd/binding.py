@@ -110,6 +110,7 @@ def lib() -> ctypes.CDLL:
             "sd_profile_enable": [i32],
             "sd_profile_read": [ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double)],
             "sd_profile_reset": [],
+            "sd_profile_times": [ctypes.POINTER(ctypes.c_float), i64, ctypes.POINTER(ctypes.c_int64)],
             "sd_release": [],
             "sd_status_string": [i32],
             "sd_last_error": [],
@@ -531,6 +532,15 @@ def sd_profile_read():
 
 def sd_profile_reset() -> None:
     check(lib().sd_profile_reset())
+
+
+def sd_profile_times():
+    """Per-launch pair-kernel times (ms) since the last reset, in launch order."""
+    cnt = ctypes.c_int64()
+    check(lib().sd_profile_times(None, 0, ctypes.byref(cnt)))
+    buf = (ctypes.c_float * max(1, cnt.value))()
+    check(lib().sd_profile_times(buf, cnt.value, ctypes.byref(cnt)))
+    return [float(buf[i]) for i in range(min(cnt.value, len(buf)))]
 
 
 def sd_release() -> None:

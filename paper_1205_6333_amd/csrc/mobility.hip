@@ -15,6 +15,7 @@
 // double.
 #include "pair_terms.h"
 #include "sd_internal.h"
+#include "sym_chunk_asm.h"
 
 #include <algorithm>
 #include <cmath>
@@ -813,8 +814,8 @@ __device__ __forceinline__ void sym_steps(SymLane (&L)[ILP], const float (&fi)[I
 // ACC: 0 plain FP32 sums, k >= 1 Kahan compensation once per k terms.
 template <int TENSOR, int ACC, int G, int ILP, bool PER>
 __device__ __forceinline__ void diag_group(SymLane (&L)[ILP], const int (&ig)[ILP],
-                                           const float4* sp, const float4* sf, int jg0,
-                                           const VConst& kc, bool& near)
+                                           const float4 (&pjv)[G], const float4 (&fjv)[G],
+                                           int jg0, const VConst& kc, bool& near)
 {
     const float gamma = kc.gamma, m3g = kc.m3g, thr2 = kc.thr2;
     float pjx[G], pjy[G], pjz[G], fjx[G], fjy[G], fjz[G];
@@ -822,8 +823,8 @@ __device__ __forceinline__ void diag_group(SymLane (&L)[ILP], const int (&ig)[IL
     float rmin = 0.0f;
 #pragma unroll
     for (int u = 0; u < G; ++u) {
-        const float4 p = sp[u];
-        const float4 f = sf[u];
+        const float4 p = pjv[u];
+        const float4 f = fjv[u];
         pjx[u] = p.x;
         pjy[u] = p.y;
         pjz[u] = p.z;
@@ -897,6 +898,22 @@ __device__ __forceinline__ void diag_group(SymLane (&L)[ILP], const int (&ig)[IL
     }
 }
 
+// j-side partials of one tile: the ROWS = BLOCK / 16 row sums of each element
+// and component added in FP64, in row order, stored as FP32 at jpart[c][I][p].
+template <int BLOCK>
+__device__ __forceinline__ void sym_tile_rows(const float* s_jacc, float* __restrict__ jpart,
+                                              const SymShape& sh, int ib, int pt)
+{
+    constexpr int ROWS = BLOCK / 16;
+    for (int t = (int)threadIdx.x; t < 3 * SYM_TJ; t += BLOCK) {
+        const int k = t / SYM_TJ, e = t % SYM_TJ;
+        double sum = 0.0;
+#pragma unroll
+        for (int r = 0; r < ROWS; ++r) sum += (double)s_jacc[(k * ROWS + r) * SYM_TJ + e];
+        jpart[((size_t)k * sh.nb + ib) * (size_t)sh.lmax + (size_t)(pt + e)] = (float)sum;
+    }
+}
+
 // Minimum resident waves per SIMD the register allocation must allow: four
 // with work-groups of 256 or 512 lanes (40 / 64 KiB of LDS: four / two
 // work-groups per CU); 128-lane groups (28 KiB) reach at most three.
@@ -964,8 +981,15 @@ k_pair_f32_sym(const float4* __restrict__ pos, const float4* __restrict__ frc, i
         }
         __syncthreads();
 #pragma unroll 1
-        for (int k = 0; k < B; k += G)
-            diag_group<TENSOR, ACC_D, G, ILP, PER>(L, ig, s_pos + k, s_frc + k, jt + k, kc, near);
+        for (int k = 0; k < B; k += G) {
+            float4 pj[G], fj[G];
+#pragma unroll
+            for (int u = 0; u < G; ++u) {
+                pj[u] = s_pos[k + u];
+                fj[u] = s_frc[k + u];
+            }
+            diag_group<TENSOR, ACC_D, G, ILP, PER>(L, ig, pj, fj, jt + k, kc, near);
+        }
         if (near && (tid & 63) == 0) flags[(size_t)ib * sh.nb + ib] = 1u;
         sym_lanes_store<ILP, BLOCK>(L, n, ib, s, pc.alpha_sum, partial);
         return;
@@ -1058,16 +1082,211 @@ k_pair_f32_sym(const float4* __restrict__ pos, const float4* __restrict__ frc, i
             near = false;
         }
         __syncthreads();   // the tile's j-side sums are complete, the next tile is staged
-        // rows added in FP64, in row order
-        for (int t = tid; t < 3 * SYM_TJ; t += BLOCK) {
-            const int k = t / SYM_TJ, e = t % SYM_TJ;
-            double sum = 0.0;
-#pragma unroll
-            for (int r = 0; r < ROWS; ++r) sum += (double)s_jacc[(k * ROWS + r) * SYM_TJ + e];
-            jpart[((size_t)k * sh.nb + ib) * (size_t)sh.lmax + (size_t)(pt + e)] = (float)sum;
-        }
+        sym_tile_rows<BLOCK>(s_jacc, jpart, sh, ib, pt);
         __syncthreads();   // s_jacc is free for the next tile
     }
+    sym_lanes_store<ILP, BLOCK>(L, n, ib, s, pc.alpha_sum, partial);
+}
+
+// Variant 2 with its chunk in assembly (sym_chunk_asm.h, generated by
+// gen_sym_chunk.py): 256 lanes, two particles per lane, Kahan blocks of 16
+// terms (one per chunk).  Same block schedule, near-pair flags, j-side rows
+// and outputs as k_pair_f32_sym; the tiles are staged as six doubled float
+// arrays (x, y, z of positions and forces), so that every component is read
+// into a register of the parity the generated code expects.
+template <int TENSOR, int ACC, bool PER>
+__global__ void __launch_bounds__(256, 4)
+k_pair_f32_sym_asm(const float4* __restrict__ pos, const float4* __restrict__ frc, int n,
+                   SymShape sh, PairConst pc, double* __restrict__ partial,
+                   float* __restrict__ jpart, uint32_t* __restrict__ flags)
+{
+    constexpr int BLOCK = 256, ILP = 2, B = 512, ROWS = BLOCK / 16;
+    constexpr int TS = 2 * SYM_TJ;     // floats of one doubled array of a tile
+    // two tiles of six doubled arrays (2 x 6 x 256), or one block of six
+    // plain arrays (6 x 512) for the diagonal work-groups
+    __shared__ float s_soa[2 * 6 * TS];
+    __shared__ float s_jacc[3 * ROWS * SYM_TJ];
+    typedef __attribute__((address_space(3))) float lds_float;
+    const int tid = threadIdx.x;
+    const bool diag = (int)blockIdx.x < sh.nb;
+    int ib, s;
+    if (diag) {
+        ib = (int)blockIdx.x;
+        s = sh.isplits;
+    } else {
+        const int w = (int)blockIdx.x - sh.nb;
+        s = w / sh.nb;
+        ib = w - s * sh.nb;
+    }
+    SymLane L[ILP];
+    sym_lanes_init<ILP, BLOCK, PER>(L, pos, n, ib);
+    const VConst kc = vconst(pc);
+    bool near = false;
+
+    if (diag) {
+        constexpr int G = 4;
+        const int jt = ib * B;
+        int ig[ILP];
+#pragma unroll
+        for (int r = 0; r < ILP; ++r) {
+            const int t = tid + r * BLOCK;
+            ig[r] = jt + t;
+            float4 rp = make_float4(far_j<PER>(), far_j<PER>(), far_j<PER>(), 0.0f);
+            float4 rf = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+            if (jt + t < n) {
+                rp = pos[jt + t];
+                rf = frc[jt + t];
+            }
+            s_soa[0 * B + t] = rp.x;
+            s_soa[1 * B + t] = rp.y;
+            s_soa[2 * B + t] = rp.z;
+            s_soa[3 * B + t] = rf.x;
+            s_soa[4 * B + t] = rf.y;
+            s_soa[5 * B + t] = rf.z;
+        }
+        __syncthreads();
+#pragma unroll 1
+        for (int k = 0; k < B; k += G) {
+            float4 pj[G], fj[G];
+#pragma unroll
+            for (int u = 0; u < G; ++u) {
+                pj[u] = make_float4(s_soa[0 * B + k + u], s_soa[1 * B + k + u],
+                                    s_soa[2 * B + k + u], 0.0f);
+                fj[u] = make_float4(s_soa[3 * B + k + u], s_soa[4 * B + k + u],
+                                    s_soa[5 * B + k + u], 0.0f);
+            }
+            diag_group<TENSOR, 4, G, ILP, PER>(L, ig, pj, fj, jt + k, kc, near);
+        }
+        if (near && (tid & 63) == 0) flags[(size_t)ib * sh.nb + ib] = 1u;
+        sym_lanes_store<ILP, BLOCK>(L, n, ib, s, pc.alpha_sum, partial);
+        return;
+    }
+
+    // lane state in the registers the generated chunk expects
+    float x0 = L[0].x, y0 = L[0].y, z0 = L[0].z, x1 = L[1].x, y1 = L[1].y, z1 = L[1].z;
+    float f0x = 0.0f, f0y = 0.0f, f0z = 0.0f, f1x = 0.0f, f1y = 0.0f, f1z = 0.0f;
+    {
+        const int i0 = ib * B + tid, i1 = i0 + BLOCK;
+        if (i0 < n) {
+            const float4 f = frc[i0];
+            f0x = f.x;
+            f0y = f.y;
+            f0z = f.z;
+        }
+        if (i1 < n) {
+            const float4 f = frc[i1];
+            f1x = f.x;
+            f1y = f.y;
+            f1z = f.z;
+        }
+    }
+    float s0x = 0.0f, s0y = 0.0f, s0z = 0.0f, s1x = 0.0f, s1y = 0.0f, s1z = 0.0f;   // sums
+    float n0x = 0.0f, n0y = 0.0f, n0z = 0.0f, n1x = 0.0f, n1y = 0.0f, n1z = 0.0f;   // -compensation
+    float k_gamma = kc.gamma, k_m3g = kc.m3g, k_thr2 = kc.thr2, k_inf = __builtin_inff();
+    asm volatile("" : "+v"(k_inf));
+    uint32_t nearf = 0;
+    const int q = tid & 15;
+    const int row = tid >> 4;
+    const int half = sh.nb >> 1;
+    const int lI = (sh.h + ((sh.extra && ib < half) ? 1 : 0)) * B;
+    const int pbeg = sh.off[s] * SYM_TJ;
+    const int pend = min(lI, sh.off[s + 1] * SYM_TJ);
+    auto tile_block = [&](int pt) { return (ib + 1 + pt / B) % sh.nb; };
+    // this thread's record of the tile at pt: position (tid < SYM_TJ) or force
+    // of particle jt + tid mod SYM_TJ
+    auto tile_load = [&](int pt) {
+        const int jt = tile_block(pt) * B + (pt % B);
+        const int j = jt + (tid & (SYM_TJ - 1));
+        const float4* src = tid < SYM_TJ ? pos : frc;
+        const float fill = tid < SYM_TJ ? far_j<PER>() : 0.0f;
+        float4 r = make_float4(fill, fill, fill, 0.0f);
+        if (j < n) r = src[j];
+        return r;
+    };
+    // element e of chunk c at slots c * 32 + e and c * 32 + 16 + e of its array
+    auto tile_store = [&](int buf, float4 r) {
+        const int e = tid & (SYM_TJ - 1);
+        float* dst = s_soa + (buf * 6 + (tid < SYM_TJ ? 0 : 3)) * TS + (e >> 4) * 32 + (e & 15);
+        dst[0] = r.x;
+        dst[16] = r.x;
+        dst[TS] = r.y;
+        dst[TS + 16] = r.y;
+        dst[2 * TS] = r.z;
+        dst[2 * TS + 16] = r.z;
+    };
+    // the next tile is read from HBM a whole tile ahead: its load is issued
+    // right after the previous one was staged, before the j-side row stores
+    float4 rec = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    if (pbeg < pend) tile_store(0, tile_load(pbeg));
+    if (pbeg + SYM_TJ < pend) rec = tile_load(pbeg + SYM_TJ);
+    __syncthreads();
+#pragma unroll 1
+    for (int pt = pbeg, buf = 0; pt < pend; pt += SYM_TJ, buf ^= 1) {
+        const bool more = pt + SYM_TJ < pend;
+        // the tile's 8 chunks in one statement: every operand is in/out, so the
+        // values stay in the registers the generated code names, with no copies;
+        // the j-side sums of each chunk go to this row's slots of s_jacc
+        uint32_t addr = (uint32_t)(uintptr_t)(lds_float*)(s_soa + buf * 6 * TS + q);
+        uint32_t jaddr = (uint32_t)(uintptr_t)(lds_float*)(s_jacc + row * SYM_TJ + q);
+        uint32_t cnt, stmp;
+        const uint32_t kmask = ACC == 32 ? 1u : 0u;   // Kahan after every chunk or every second
+#define SD_SYM_TILE_CALL(TEXT)                                                                 \
+    asm volatile(TEXT                                                                          \
+                 : [s0x] "+" SD_SYM_R_S0x(s0x), [s0y] "+" SD_SYM_R_S0y(s0y),                   \
+                   [s0z] "+" SD_SYM_R_S0z(s0z), [s1x] "+" SD_SYM_R_S1x(s1x),                   \
+                   [s1y] "+" SD_SYM_R_S1y(s1y), [s1z] "+" SD_SYM_R_S1z(s1z),                   \
+                   [y0x] "+" SD_SYM_R_Y0x(n0x), [y0y] "+" SD_SYM_R_Y0y(n0y),                   \
+                   [y0z] "+" SD_SYM_R_Y0z(n0z), [y1x] "+" SD_SYM_R_Y1x(n1x),                   \
+                   [y1y] "+" SD_SYM_R_Y1y(n1y), [y1z] "+" SD_SYM_R_Y1z(n1z),                   \
+                   [x0] "+" SD_SYM_R_X0x(x0), [y0] "+" SD_SYM_R_X0y(y0), [z0] "+" SD_SYM_R_X0z(z0), \
+                   [x1] "+" SD_SYM_R_X1x(x1), [y1] "+" SD_SYM_R_X1y(y1), [z1] "+" SD_SYM_R_X1z(z1), \
+                   [f0x] "+" SD_SYM_R_FI0x(f0x), [f0y] "+" SD_SYM_R_FI0y(f0y),                 \
+                   [f0z] "+" SD_SYM_R_FI0z(f0z), [f1x] "+" SD_SYM_R_FI1x(f1x),                 \
+                   [f1y] "+" SD_SYM_R_FI1y(f1y), [f1z] "+" SD_SYM_R_FI1z(f1z),                 \
+                   [adr] "+" SD_SYM_R_ADDR(addr), [jadr] "+" SD_SYM_R_JADDR(jaddr),            \
+                   [nf] "+s"(nearf), [cnt] "=&s"(cnt), [tmp] "=&s"(stmp)                       \
+                 : [gam] SD_SYM_R_GAMMA(k_gamma), [thr] SD_SYM_R_THR2(k_thr2),                 \
+                   [thro] SD_SYM_R_THR2O(k_thr2), [inf] SD_SYM_R_INF(k_inf),                   \
+                   [m3g] SD_SYM_R_M3G(k_m3g), [kmask] "s"(kmask)                               \
+                 : SD_SYM_CLOBBERS, "vcc", "scc", "memory")
+        if constexpr (TENSOR == T_RPY && !PER)
+            SD_SYM_TILE_CALL(SD_SYM_TILE_RPY_FREE);
+        else if constexpr (TENSOR == T_RPY)
+            SD_SYM_TILE_CALL(SD_SYM_TILE_RPY_PER);
+        else if constexpr (!PER)
+            SD_SYM_TILE_CALL(SD_SYM_TILE_OSEEN_FREE);
+        else
+            SD_SYM_TILE_CALL(SD_SYM_TILE_OSEEN_PER);
+#undef SD_SYM_TILE_CALL
+        if (more) {
+            tile_store(buf ^ 1, rec);
+            if (pt + 2 * SYM_TJ < pend) rec = tile_load(pt + 2 * SYM_TJ);
+        }
+        if (nearf) {
+            const int J = tile_block(pt);
+            if ((tid & 63) == 0) {
+                flags[(size_t)ib * sh.nb + J] = 1u;
+                flags[(size_t)J * sh.nb + ib] = 1u;
+            }
+            nearf = 0;
+        }
+        __syncthreads();   // the tile's j-side sums are complete, the next tile is staged
+        sym_tile_rows<BLOCK>(s_jacc, jpart, sh, ib, pt);
+        __syncthreads();   // s_jacc is free for the next tile
+    }
+    // i side: S - C = S + NC (the negated compensation)
+    L[0].s0 = s0x;
+    L[0].s1 = s0y;
+    L[0].s2 = s0z;
+    L[1].s0 = s1x;
+    L[1].s1 = s1y;
+    L[1].s2 = s1z;
+    L[0].c0 = -n0x;
+    L[0].c1 = -n0y;
+    L[0].c2 = -n0z;
+    L[1].c0 = -n1x;
+    L[1].c1 = -n1y;
+    L[1].c2 = -n1z;
     sym_lanes_store<ILP, BLOCK>(L, n, ib, s, pc.alpha_sum, partial);
 }
 
@@ -1329,12 +1548,23 @@ static hipError_t launch_f32_sym(const PairLaunch& L, const float4* pos, const f
     float* jpart = (float*)((char*)partial + sym_jpart_offset(L, n));
     uint32_t* flags = (uint32_t*)((char*)partial + sym_flags_offset(L, n));
     dim3 grid(sh.nb * sh.isplits + sh.nb), block(BLOCK);
-    if (pc.box > 0.0)
-        hipLaunchKernelGGL((k_pair_f32_sym<TENSOR, ACC, BLOCK, ILP, true>), grid, block, 0, st,
-                           pos, frc, n, sh, pc, partial, jpart, flags);
-    else
-        hipLaunchKernelGGL((k_pair_f32_sym<TENSOR, ACC, BLOCK, ILP, false>), grid, block, 0, st,
-                           pos, frc, n, sh, pc, partial, jpart, flags);
+    if constexpr (ACC == 16 || ACC == 32) {
+        static_assert(BLOCK == 256 && ILP == 2, "Kahan blocks of 16 or 32: the assembly shape");
+        // the shape with its chunk in assembly
+        if (pc.box > 0.0)
+            hipLaunchKernelGGL((k_pair_f32_sym_asm<TENSOR, ACC, true>), grid, block, 0, st, pos,
+                               frc, n, sh, pc, partial, jpart, flags);
+        else
+            hipLaunchKernelGGL((k_pair_f32_sym_asm<TENSOR, ACC, false>), grid, block, 0, st, pos,
+                               frc, n, sh, pc, partial, jpart, flags);
+    } else {
+        if (pc.box > 0.0)
+            hipLaunchKernelGGL((k_pair_f32_sym<TENSOR, ACC, BLOCK, ILP, true>), grid, block, 0,
+                               st, pos, frc, n, sh, pc, partial, jpart, flags);
+        else
+            hipLaunchKernelGGL((k_pair_f32_sym<TENSOR, ACC, BLOCK, ILP, false>), grid, block, 0,
+                               st, pos, frc, n, sh, pc, partial, jpart, flags);
+    }
     return hipGetLastError();
 }
 
@@ -1365,7 +1595,10 @@ static hipError_t launch_f32_b(const PairLaunch& L, const float4* pos, const flo
                                hipStream_t st)
 {
     if (L.variant == 2) {
-        if constexpr (ACC == 0 || ACC == 4 || ACC == 8 || ACC == 16) {
+        if constexpr (ACC == 16 || ACC == 32) {   // the assembly shape only
+            if (L.block == 256 && L.ilp == 2)
+                return launch_f32_sym<TENSOR, ACC, 256, 2>(L, pos, frc, n, pc, partial, st);
+        } else if constexpr (ACC == 0 || ACC == 4 || ACC == 8) {
             if (L.block == 128 && L.ilp == 1)
                 return launch_f32_sym<TENSOR, ACC, 128, 1>(L, pos, frc, n, pc, partial, st);
             if (L.block == 256 && L.ilp == 1)
@@ -1402,6 +1635,7 @@ hipError_t launch_pair_f32(const PairLaunch& L, int tensor, int acc, const float
     case 4: return launch_f32_b<T, 4>(L, pos, frc, x64, n, pc, partial, st);         \
     case 8: return launch_f32_b<T, 8>(L, pos, frc, x64, n, pc, partial, st);         \
     case 16: return launch_f32_b<T, 16>(L, pos, frc, x64, n, pc, partial, st);       \
+    case 32: return launch_f32_b<T, 32>(L, pos, frc, x64, n, pc, partial, st);       \
     default: return hipErrorInvalidValue;                                            \
     }
     if (tensor == T_OSEEN) { SD_ACC(T_OSEEN) }

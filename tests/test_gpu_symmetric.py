@@ -58,26 +58,31 @@ def _cfg(block, splits, kb, ilp=1):
     return dict(variant=2, block=block, splits=splits, ilp=ilp, kahan_block=kb)
 
 
-# (work-group size, particles per lane): blocks of 128 to 512 particles
-SHAPES = [(128, 1), (256, 1), (512, 1), (128, 2), (256, 2)]
+# (work-group size, particles per lane, Kahan block): blocks of 128 to 512
+# particles; (256, 2, 16) and (256, 2, 32) run their chunks in generated assembly
+SHAPES = [(128, 1, 8), (256, 1, 8), (512, 1, 8), (128, 2, 8), (256, 2, 8), (256, 2, 16),
+          (256, 2, 32)]
 
 
 @pytest.mark.parametrize("n", [1, 2, 17, 128, 129, 255, 256, 257, 511, 512, 513, 769, 1000,
                                1337, 2049])
-@pytest.mark.parametrize("block,ilp", SHAPES)
-def test_sym_sizes(sd, orc, n, block, ilp):
+@pytest.mark.parametrize("block,ilp,kb", SHAPES)
+def test_sym_sizes(sd, orc, n, block, ilp, kb):
     x = W.random_suspension(n, seed=400 + n)
     f = W.gaussian_forces(n, seed=500 + n)
     ref = orc.mobility(orc.params(), W.round_to_f32(x), W.round_to_f32(f))
     for splits in (1, 3, 1000):
-        v = _apply(sd, x, f, 0, sd.params(), _cfg(block, splits, 8, ilp))
+        v = _apply(sd, x, f, 0, sd.params(), _cfg(block, splits, kb, ilp))
         _check(v, ref, 0, n, block, ilp, splits)
 
 
-@pytest.mark.parametrize("kb,prec", [(0, 2), (4, 0), (8, 0)])
+@pytest.mark.parametrize("kb,prec", [(0, 2), (4, 0), (8, 0), (16, 0), (32, 0)])
 @pytest.mark.parametrize("tensor", [0, 1])
 @pytest.mark.parametrize("ilp", [1, 2])
 def test_sym_accumulation_and_tensor(sd, orc, kb, prec, tensor, ilp):
+    if kb >= 16 and ilp != 2:
+        pytest.skip("Kahan blocks of 16 and 32 exist for the assembly shape (two particles "
+                    "per lane) only")
     n = 3001
     x = W.random_suspension(n, seed=410)
     f = W.gaussian_forces(n, seed=411)
@@ -97,8 +102,8 @@ def test_sym_overlapping_pairs(sd, orc, tensor, overlap):
     po = orc.params(a=1.3, eta=0.21, tensor=tensor, overlap=overlap)
     ps = sd.params(1.3, 0.21, tensor, overlap)
     ref = orc.mobility(po, W.round_to_f32(x), W.round_to_f32(f))
-    for block, ilp in SHAPES:
-        v = _apply(sd, x, f, 0, ps, _cfg(block, 2, 8, ilp))
+    for block, ilp, kb in SHAPES:
+        v = _apply(sd, x, f, 0, ps, _cfg(block, 2, kb, ilp))
         _check(v, ref, 0, tensor, overlap, block, ilp)
 
 
@@ -110,8 +115,8 @@ def test_sym_coincident_spheres(sd, orc):
     f = W.gaussian_forces(n, seed=442)
     for overlap in (False, True):
         ref = orc.mobility(orc.params(overlap=overlap), W.round_to_f32(x), W.round_to_f32(f))
-        for block, ilp in SHAPES:
-            v = _apply(sd, x, f, 0, sd.params(overlap=overlap), _cfg(block, 3, 8, ilp))
+        for block, ilp, kb in SHAPES:
+            v = _apply(sd, x, f, 0, sd.params(overlap=overlap), _cfg(block, 3, kb, ilp))
             assert np.all(np.isfinite(v))
             _check(v, ref, 0, overlap, block, ilp)
 
@@ -123,8 +128,8 @@ def test_sym_periodic(sd, orc, n):
     x, L = W.periodic_suspension(n, phi=0.2, min_dist=2.02, seed=450 + n)
     f = W.gaussian_forces(n, seed=451)
     ref = orc.mobility(orc.params(box=L), W.round_to_f32(x), W.round_to_f32(f))
-    for block, ilp in SHAPES:
-        v = _apply(sd, x, f, 0, sd.params(box=L), _cfg(block, 5, 8, ilp))
+    for block, ilp, kb in SHAPES:
+        v = _apply(sd, x, f, 0, sd.params(box=L), _cfg(block, 5, kb, ilp))
         _check(v, ref, 0, n, block, ilp)
 
 
@@ -138,7 +143,13 @@ def test_sym_matches_variant0_and_is_deterministic(sd):
     b = _apply(sd, x, f, 0, p, dict(variant=0, block=256, splits=8, ilp=1, kahan_block=8))
     assert rel2(a, b) <= 1e-6
     assert rowerr(a, b) <= 1e-5
-    sd.sd_set_kernel_config(0, _cfg(256, 8, 8))
+    for cfg in (_cfg(256, 8, 8), _cfg(256, 8, 16, 2)):
+        _deterministic(sd, x, f, p, cfg)
+
+
+def _deterministic(sd, x, f, p, cfg):
+    import torch
+    sd.sd_set_kernel_config(0, cfg)
     try:
         pos, frc = to_dev4(x, torch.float32), to_dev4(f, torch.float32)
         ref = sd.mobility_apply(pos, frc, params=p).clone()
@@ -157,8 +168,8 @@ def test_sym_time_loop(sd, orc):
     x0 = W.random_suspension(n, phi=0.2, min_dist=2.0, seed=471)
     f = W.gravity_forces(n) + 0.3 * W.gaussian_forces(n, seed=472)
     xr, vr, _ = orc.run(orc.params(overlap=True), x0, W.round_to_f32(f), 0.005, 40, orc.AB2)
-    for block, ilp in SHAPES:
-        sd.sd_set_kernel_config(0, _cfg(block, 3, 8, ilp))
+    for block, ilp, kb in SHAPES:
+        sd.sd_set_kernel_config(0, _cfg(block, 3, kb, ilp))
         try:
             xd = torch.tensor(x0, dtype=torch.float64, device="cuda")
             vp = torch.zeros_like(xd)
@@ -189,8 +200,8 @@ def test_sym_near_pairs_between_many_blocks(sd, orc):
     f = W.gaussian_forces(2 * m, seed=483)
     for overlap in (True, False):
         ref = orc.mobility(orc.params(overlap=overlap), W.round_to_f32(x), W.round_to_f32(f))
-        for block, ilp in SHAPES:
-            v = _apply(sd, x, f, 0, sd.params(overlap=overlap), _cfg(block, 3, 8, ilp))
+        for block, ilp, kb in SHAPES:
+            v = _apply(sd, x, f, 0, sd.params(overlap=overlap), _cfg(block, 3, kb, ilp))
             _check(v, ref, 0, overlap, block, ilp)
 
 
