@@ -412,7 +412,7 @@ typedef struct sd_kernel_config {
                              chunk loop in generated assembly); library
                              workspace of about 6 n^2 / (block * ilp)
                              bytes.  The automatic choice takes it from
-                             n = 32768 on (block 256, ilp 2, kahan_block
+                             n = 16384 on (block 256, ilp 2, kahan_block
                              32 for SD_FP32_KAHAN) while that workspace
                              stays within 1 GiB */
     int32_t block;        /* work-group size (64, 128 or 256; variant 2: 128,

@@ -1,6 +1,7 @@
 // integrate.hip -- O(N) kernels of the time loop (Sec. 3.1, step 1) and small
 // helpers: FP64 -> FP32 staging of positions, split merge fused with the
 // Euler / AB2 position update, packing and axpy for the adjoint loop.
+#include "pair_terms.h"
 #include "sd_internal.h"
 
 namespace sd {
@@ -60,12 +61,7 @@ k_merge_integrate(const double* __restrict__ partial, int S, int n, const F4* __
     if (i >= n) return;
     const F4 f = frc[i];
     double v[3] = { mu0 * (double)f.x, mu0 * (double)f.y, mu0 * (double)f.z };
-    for (int s = 0; s < S; ++s) {
-        const size_t base = (size_t)s * 3 * (size_t)n + (size_t)i;
-        v[0] += partial[base];
-        v[1] += partial[base + (size_t)n];
-        v[2] += partial[base + 2 * (size_t)n];
-    }
+    add_split_rows(partial, S, n, i, v[0], v[1], v[2]);
     double xn[3];
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
@@ -86,12 +82,7 @@ __global__ void __launch_bounds__(256) k_sum_partials(const double* __restrict__
     const int i = blockIdx.x * 256 + threadIdx.x;
     if (i >= n) return;
     double g[3] = { 0.0, 0.0, 0.0 };
-    for (int s = 0; s < S; ++s) {
-        const size_t base = (size_t)s * 3 * (size_t)n + (size_t)i;
-        g[0] += partial[base];
-        g[1] += partial[base + (size_t)n];
-        g[2] += partial[base + 2 * (size_t)n];
-    }
+    add_split_rows(partial, S, n, i, g[0], g[1], g[2]);
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
         const size_t e = 3 * (size_t)i + k;

@@ -1339,12 +1339,30 @@ k_sym_fold_near(const float* __restrict__ jpart, const float4* __restrict__ pos,
     const size_t cs = (size_t)nb * (size_t)sh.lmax;
     double v0 = 0.0, v1 = 0.0, v2 = 0.0;
     if (q < n) {
-        for (int d = 1; d <= sh.h; ++d) {
-            const int I = (J - d + nb) % nb;
-            const size_t at = (size_t)I * sh.lmax + (size_t)(d - 1) * B + o;
-            v0 += (double)jpart[at];
-            v1 += (double)jpart[cs + at];
-            v2 += (double)jpart[2 * cs + at];
+        // blocks I = J - d (d = 1 .. h) in that order, the loads of a group of
+        // them issued before its adds
+        constexpr int G = 8;
+        for (int d0 = 1; d0 <= sh.h; d0 += G) {
+            float a[G][3];
+#pragma unroll
+            for (int u = 0; u < G; ++u) {
+                const int d = d0 + u;
+                if (d <= sh.h) {
+                    const int I = (J - d + nb) % nb;
+                    const size_t at = (size_t)I * sh.lmax + (size_t)(d - 1) * B + o;
+                    a[u][0] = jpart[at];
+                    a[u][1] = jpart[cs + at];
+                    a[u][2] = jpart[2 * cs + at];
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < G; ++u) {
+                if (d0 + u <= sh.h) {
+                    v0 += (double)a[u][0];
+                    v1 += (double)a[u][1];
+                    v2 += (double)a[u][2];
+                }
+            }
         }
         if (sh.extra) {
             const int I = (J + half) % nb;
@@ -1502,12 +1520,7 @@ k_merge(const double* __restrict__ partial, int S, int n, const F4* __restrict__
     if (i >= n) return;
     const F4 f = frc[i];
     double v0 = mu0 * (double)f.x, v1 = mu0 * (double)f.y, v2 = mu0 * (double)f.z;
-    for (int s = 0; s < S; ++s) {
-        const size_t base = (size_t)s * 3 * (size_t)n + (size_t)i;
-        v0 += partial[base];
-        v1 += partial[base + (size_t)n];
-        v2 += partial[base + 2 * (size_t)n];
-    }
+    add_split_rows(partial, S, n, i, v0, v1, v2);
     vel[3 * (size_t)i + 0] = v0;
     vel[3 * (size_t)i + 1] = v1;
     vel[3 * (size_t)i + 2] = v2;

@@ -41,4 +41,38 @@ __device__ __forceinline__ void near_term(const PairConst& pc, double d0, double
     n2 += cI * f2 + cD * dF * d2;
 }
 
+// v += rows s = 0, 1, ..., S-1 of a split-row array (component c of particle
+// i of row s at partial[(3 s + c) n + i]), added in that order.  The loads of
+// ROWS_IN_FLIGHT rows are issued before the first of their adds, so a thread
+// waits for memory once per group of rows rather than once per row; the sum
+// is the one of the plain loop, bit for bit.
+constexpr int ROWS_IN_FLIGHT = 8;
+
+__device__ __forceinline__ void add_split_rows(const double* __restrict__ partial, int S, int n,
+                                               int i, double& v0, double& v1, double& v2)
+{
+    const size_t rs = 3 * (size_t)n;
+    const double* p = partial + i;
+    for (int s0 = 0; s0 < S; s0 += ROWS_IN_FLIGHT) {
+        double a[ROWS_IN_FLIGHT][3];
+#pragma unroll
+        for (int u = 0; u < ROWS_IN_FLIGHT; ++u) {
+            if (s0 + u < S) {
+                const double* q = p + (size_t)(s0 + u) * rs;
+                a[u][0] = q[0];
+                a[u][1] = q[n];
+                a[u][2] = q[2 * (size_t)n];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < ROWS_IN_FLIGHT; ++u) {
+            if (s0 + u < S) {
+                v0 += a[u][0];
+                v1 += a[u][1];
+                v2 += a[u][2];
+            }
+        }
+    }
+}
+
 }  // namespace sd

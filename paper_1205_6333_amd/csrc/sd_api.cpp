@@ -239,14 +239,15 @@ sd_kernel_config default_config(int32_t prec, int64_t n)
     c.splits = (int32_t)s;
     // From n = SYM_MIN_N on, the pair-symmetric kernel (each pair of particles
     // in different blocks evaluated once) with two particles per lane,
-    // whenever its j-side workspace fits.  Measured (ms per product, wall
-    // clock, one box): N = 65536: variant 0 2.14, variant 2 1.83 (32 splits;
-    // one particle per lane 1.96).  N = 16384: variant 0 0.162, variant 2 at
-    // best 0.172; N = 8192: 0.063 vs 0.081; N = 4096: 0.032 vs 0.051 (the
-    // fold and the fixed cost per work-group do not pay off there).
+    // whenever its j-side workspace fits.  Measured (ms per pair-kernel
+    // launch, one box): N = 65536: variant 0 2.10, variant 2 1.45;
+    // N = 32768: 0.551 vs 0.388; N = 24576: 0.332 vs 0.229; N = 16384: 0.166
+    // vs 0.116.
     if (prec != SD_FP64 && n >= SYM_MIN_N && sym_fits(n, 2 * c.block)) {
         c.variant = 2;
         c.ilp = 2;
+        // (N = 16384: 0.119 ms per launch at 16 splits, 0.116 at 32, 0.120 at 64)
+        c.splits = std::min<int32_t>(c.splits, 32);
         // Kahan blocks of 32 terms select the chunk loop in generated assembly
         // (N = 65536: 1.45 ms per pair-kernel launch against 1.73 for the
         // compiled loop with blocks of 8)

@@ -46,7 +46,7 @@ sd_kernel_config default_config(int32_t prec, int64_t n);
 // particles in blocks of `block` stays within SYM_WORKSPACE_CAP bytes.
 constexpr size_t SYM_WORKSPACE_CAP = (size_t)1 << 30;
 // Smallest n for which the automatic configuration takes variant 2.
-constexpr int64_t SYM_MIN_N = 32768;
+constexpr int64_t SYM_MIN_N = 16384;
 bool sym_fits(int64_t n, int block);
 sd_kernel_config choose_config(int32_t prec, int64_t n);
 void set_tuned_config(int32_t prec, int64_t n, const sd_kernel_config& c);
