@@ -467,6 +467,27 @@ sd_status sd_profile_times(float* ms, int64_t cap, int64_t* count);
  */
 sd_status sd_mean_vector(int64_t n, const double* v, double* out, void* stream);
 
+/*
+ * sd_premise_counts -- pairs that break the premise of the far-field tensor.
+ * The Rotne-Prager tensor of Eq. 4 keeps the mobility matrix positive definite
+ * only while every pair distance is r >= 2a (Sec. 2.2).  The product kernels
+ * (mobility_apply, mobility_apply_noalloc, sd_step, sd_run, sd_run_lub; every
+ * precision and kernel variant) count on their device the unordered pairs
+ * i < j they meet with 0 < r < 2a (*sub2a) and with r = 0 (*coincident:
+ * distinct particles at one point); r is the FP64 distance the pair's near-field
+ * evaluation uses (FP64 master positions in the time loops, the staged FP32
+ * positions in mobility_apply; nearest image in a periodic box).  Under
+ * SD_OVERLAP_NONE these pairs were evaluated with the far form of Eq. 4
+ * (coincident ones contribute nothing); under SD_OVERLAP_RPY with the overlap
+ * form.  The counts accumulate over calls until a read with reset != 0 zeroes
+ * them; calls on several streams of one device share them.  The batched,
+ * cluster and adjoint entry points do not count.
+ *   sub2a, coincident  host int64 (either may be NULL)
+ * Reads the current device's counters in stream order and synchronises the
+ * stream; SD_EDEVICE if that fails.
+ */
+sd_status sd_premise_counts(int64_t* sub2a, int64_t* coincident, int32_t reset, void* stream);
+
 /* --------------------------------------------------------------------- misc */
 
 /*

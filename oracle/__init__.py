@@ -61,6 +61,8 @@ def _load():
         lib.oracle_mobility.argtypes = [P, i64, d, d, d]
         lib.oracle_mobility_rows.argtypes = [P, i64, d, d, i64, ctypes.POINTER(i64), d]
         lib.oracle_dense_mobility.argtypes = [P, i64, d, d]
+        lib.oracle_premise_counts.argtypes = [P, i64, d, ctypes.POINTER(i64)]
+        lib.oracle_premise_counts.restype = None
         lib.oracle_run.argtypes = [P, i64, d, d, ctypes.c_double, i64, i64, ctypes.c_int, d, d, i64]
         lib.oracle_run.restype = ctypes.c_int
         lib.oracle_pair_grad.argtypes = [P, d, d, d, d]
@@ -129,6 +131,15 @@ def mobility(p: OracleParams, x, f) -> np.ndarray:
     v = np.empty_like(x)
     _load().oracle_mobility(ctypes.byref(p), x.shape[0], _ptr(x), _ptr(f), _ptr(v))
     return v
+
+
+def premise_counts(p: OracleParams, x):
+    """(pairs i < j with 0 < r < 2a, pairs with r = 0): the pairs that break
+    the premise r >= 2a of Eq. 4 (Sec. 2.2), nearest image in a box."""
+    x = _vec(x)
+    out = (ctypes.c_int64 * 2)()
+    _load().oracle_premise_counts(ctypes.byref(p), x.shape[0], _ptr(x), out)
+    return int(out[0]), int(out[1])
 
 
 def mobility_rows(p: OracleParams, x, f, rows) -> np.ndarray:

@@ -150,6 +150,29 @@ static void velocity_of(const oracle_params* p, int64_t n, const double* x, cons
     out[0] = v[0]; out[1] = v[1]; out[2] = v[2];
 }
 
+/* Pairs that break the premise of the far-field tensor: the Rotne-Prager
+ * tensor of Eq. (4) keeps the mobility matrix positive definite only while
+ * every pair distance is r >= 2a (Sec. 2.2).  Counts the unordered pairs
+ * i < j with 0 < r < 2a (out[0]) and with r = 0 (out[1]), r the nearest-image
+ * distance; r < 2a is tested as r^2 < 4 a^2. */
+void oracle_premise_counts(const oracle_params* p, int64_t n, const double* x, int64_t out[2])
+{
+    int64_t sub = 0, co = 0;
+    for (int64_t i = 0; i < n; ++i)
+        for (int64_t j = i + 1; j < n; ++j) {
+            double r[3] = { x[3 * i + 0] - x[3 * j + 0], x[3 * i + 1] - x[3 * j + 1],
+                            x[3 * i + 2] - x[3 * j + 2] };
+            nearest_image(p, r);
+            const double r2 = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
+            if (r2 == 0.0)
+                ++co;
+            else if (r2 < 4.0 * p->a * p->a)
+                ++sub;
+        }
+    out[0] = sub;
+    out[1] = co;
+}
+
 /* All-pairs mobility product, Eq. (7a), step 3 of the algorithm of Sec. 3.1.
  * x, f, v: n x 3 row-major (AoS). */
 void oracle_mobility(const oracle_params* p, int64_t n, const double* x, const double* f, double* v)

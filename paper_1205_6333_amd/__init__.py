@@ -14,7 +14,8 @@ from .binding import (SD_AB2, SD_EULER, SD_FP32_KAHAN, SD_FP32_PLAIN, SD_FP64, S
                       sd_profile_reset, sd_profile_times, sd_release, sd_run, sd_run_adjoint,
                       sd_run_batched,
                       sd_set_kernel_config, sd_step, sd_version)
-from .binding import lub, lubrication_forces, sd_mean_vector, sd_pack, sd_run_lub  # noqa: E402,F401
+from .binding import (lub, lubrication_forces, sd_mean_vector, sd_pack,  # noqa: E402,F401
+                      sd_premise_counts, sd_run_lub)
 from . import autograd  # noqa: E402,F401
 from .binding import (SD_ACC_DS, SD_ACC_FP32, SD_ACC_FP64, SD_ACC_KAHAN, SD_POS_DS,  # noqa: E402,F401
                       SD_POS_FP32, SD_POS_FP64, cluster_frames, sd_cluster_run)

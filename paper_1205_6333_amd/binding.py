@@ -104,6 +104,8 @@ def lib() -> ctypes.CDLL:
             "lubrication_forces": [P, ctypes.POINTER(SdLub), i64, dp, dp, dp, dp, vp],
             "sd_run_lub": [P, ctypes.POINTER(SdLub), i64, dp, dp, dp, d, i64, i64, i32, i32, vp],
             "sd_mean_vector": [i64, dp, dp, vp],
+            "sd_premise_counts": [ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64),
+                                  i32, vp],
             "sd_set_graph_mode": [i32],
             "sd_cluster_run": [P, i64, i32, ctypes.POINTER(SdClusterSpec), dp, dp, dp, vp],
             "sd_membench": [i32, i32, i32, i64, vp, vp, vp],
@@ -494,6 +496,16 @@ def sd_mean_vector(v, out=None, stream=None):
     _vec3(out, 1, "out")
     check(lib().sd_mean_vector(n, _ptr(v), _ptr(out), _stream(stream)))
     return out
+
+
+def sd_premise_counts(reset: bool = False, stream=None):
+    """(pairs with 0 < r < 2a, coincident pairs) met by the product kernels on
+    the current device since the last reset (the premise r >= 2a of Eq. 4)."""
+    sub = ctypes.c_int64()
+    co = ctypes.c_int64()
+    check(lib().sd_premise_counts(ctypes.byref(sub), ctypes.byref(co), int(bool(reset)),
+                                  _stream(stream)))
+    return int(sub.value), int(co.value)
 
 
 def sd_set_kernel_config(precision: int, cfg: Optional[dict]) -> None:

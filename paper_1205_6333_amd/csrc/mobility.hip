@@ -162,6 +162,16 @@ __device__ __forceinline__ void near_diff(const LaneF32& L, const float4 pj, int
     }
 }
 
+// Unordered pairs i < j met by the product kernels on this device that break
+// the premise r >= 2a of Eq. 4: [0] with 0 < r < 2a, [1] with r = 0.  Counted
+// on the rare FP64 near-pair branch only, by the evaluation of row min(i, j).
+__device__ unsigned long long g_premise[2];
+
+__device__ __forceinline__ void count_premise(int cls)
+{
+    if (cls != PREMISE_OK) atomicAdd(&g_premise[cls - 1], 1ull);
+}
+
 // One pair (i, j) on the FP32 fast path.  pj/fj: position and force of j
 // (wave-uniform).  jg: global index of j, used only on the near branch.
 template <int TENSOR, bool KAHAN, bool PER>
@@ -214,8 +224,9 @@ __device__ __forceinline__ void pair_f32(LaneF32& L, const float4 pj, const floa
         if (jg != L.i && L.i < n && jg < n) {
             double d0, d1, d2;
             near_diff<PER>(L, pj, jg, pc, x64, d0, d1, d2);
-            near_term<TENSOR>(pc, d0, d1, d2, (double)fj.x, (double)fj.y, (double)fj.z, L.n0,
-                              L.n1, L.n2);
+            const int cls = near_term<TENSOR>(pc, d0, d1, d2, (double)fj.x, (double)fj.y,
+                                              (double)fj.z, L.n0, L.n1, L.n2);
+            if (L.i < jg) count_premise(cls);
         }
     }
 }
@@ -233,7 +244,9 @@ __device__ __forceinline__ void near_pair_lds(const LaneF32& L, const float4 pj,
     double d0, d1, d2;
     near_diff<PER>(L, pj, jg, pc, x64, d0, d1, d2);
     double n0 = slot[0], n1 = slot[stride], n2 = slot[2 * stride];
-    near_term<TENSOR>(pc, d0, d1, d2, (double)fj.x, (double)fj.y, (double)fj.z, n0, n1, n2);
+    const int cls =
+        near_term<TENSOR>(pc, d0, d1, d2, (double)fj.x, (double)fj.y, (double)fj.z, n0, n1, n2);
+    if (L.i < jg) count_premise(cls);
     slot[0] = n0;
     slot[stride] = n1;
     slot[2 * stride] = n2;
@@ -1414,8 +1427,9 @@ k_sym_fold_near(const float* __restrict__ jpart, const float4* __restrict__ pos,
                     const float4 fj = s_frc[e];
                     double d0, d1, d2;
                     near_diff_v<PER>(xq, yq, zq, q, pj, jg, pc, x64, d0, d1, d2);
-                    near_term<TENSOR>(pc, d0, d1, d2, (double)fj.x, (double)fj.y, (double)fj.z,
-                                      v0, v1, v2);
+                    const int cls = near_term<TENSOR>(pc, d0, d1, d2, (double)fj.x,
+                                                      (double)fj.y, (double)fj.z, v0, v1, v2);
+                    if (q < jg) count_premise(cls);
                 }
             }
         }
@@ -1498,7 +1512,10 @@ k_pair_f64_lds(const double4* __restrict__ pos, const double4* __restrict__ frc,
             v0 = fma(A, fj.x, fma(sB, dx, v0));
             v1 = fma(A, fj.y, fma(sB, dy, v1));
             v2 = fma(A, fj.z, fma(sB, dz, v2));
-            if (nr && (jt + k) != i && i < n && (jt + k) < n) near_term<TENSOR>(pc, dx, dy, dz, fj.x, fj.y, fj.z, n0, n1, n2);
+            if (nr && (jt + k) != i && i < n && (jt + k) < n) {
+                const int cls = near_term<TENSOR>(pc, dx, dy, dz, fj.x, fj.y, fj.z, n0, n1, n2);
+                if (i < jt + k) count_premise(cls);
+            }
         }
     }
     if (i < n) {
@@ -1680,6 +1697,29 @@ hipError_t launch_pair_f64(const PairLaunch& L, int tensor, const double4* pos, 
     SD_CASE(64) SD_CASE(128) SD_CASE(256) SD_CASE(512)
 #undef SD_CASE
     return hipErrorInvalidValue;
+}
+
+__global__ void k_premise_clear(unsigned long long* c)
+{
+    if (threadIdx.x < 2) c[threadIdx.x] = 0ull;
+}
+
+hipError_t premise_counts(int64_t* sub2a, int64_t* coincident, bool reset, hipStream_t st)
+{
+    // the counters of the current device (each device holds its own copy)
+    void* dev = nullptr;
+    hipError_t e = hipGetSymbolAddress(&dev, HIP_SYMBOL(g_premise));
+    if (e != hipSuccess) return e;
+    unsigned long long h[2] = { 0ull, 0ull };
+    if ((e = hipMemcpyAsync(h, dev, sizeof h, hipMemcpyDeviceToHost, st)) != hipSuccess) return e;
+    if (reset) {
+        hipLaunchKernelGGL(k_premise_clear, dim3(1), dim3(64), 0, st, (unsigned long long*)dev);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    if ((e = hipStreamSynchronize(st)) != hipSuccess) return e;
+    if (sub2a) *sub2a = (int64_t)h[0];
+    if (coincident) *coincident = (int64_t)h[1];
+    return hipSuccess;
 }
 
 hipError_t launch_merge_f32(const double* partial, int splits, int n, const float4* frc, double mu0,

@@ -7,11 +7,16 @@
 
 namespace sd {
 
-// FP64 contribution of one near pair (d = x_i - x_j, r^2 below threshold) to v_i.
+// FP64 contribution of one near pair (d = x_i - x_j, r^2 below threshold) to
+// v_i.  Returns the pair's standing against the premise r >= 2a under which
+// the tensor of Eq. 4 is positive definite (Sec. 2.2): PREMISE_OK for
+// r >= 2a, PREMISE_SUB2A for 0 < r < 2a, PREMISE_COINCIDENT for r = 0.
+enum { PREMISE_OK = 0, PREMISE_SUB2A = 1, PREMISE_COINCIDENT = 2 };
+
 template <int TENSOR>
-__device__ __forceinline__ void near_term(const PairConst& pc, double d0, double d1, double d2,
-                                          double f0, double f1, double f2, double& n0, double& n1,
-                                          double& n2)
+__device__ __forceinline__ int near_term(const PairConst& pc, double d0, double d1, double d2,
+                                         double f0, double f1, double f2, double& n0, double& n1,
+                                         double& n2)
 {
     const double r2 = d0 * d0 + d1 * d1 + d2 * d2;
     if (r2 == 0.0) {  // coincident distinct spheres: limit of the overlap form, else nothing
@@ -20,7 +25,7 @@ __device__ __forceinline__ void near_term(const PairConst& pc, double d0, double
             n1 += pc.mu0 * f1;
             n2 += pc.mu0 * f2;
         }
-        return;
+        return PREMISE_COINCIDENT;
     }
     const double r = sqrt(r2);
     double cI, cD;  // T = cI I + cD d d
@@ -39,6 +44,7 @@ __device__ __forceinline__ void near_term(const PairConst& pc, double d0, double
     n0 += cI * f0 + cD * dF * d0;
     n1 += cI * f1 + cD * dF * d1;
     n2 += cI * f2 + cD * dF * d2;
+    return r2 < 4.0 * pc.a * pc.a ? PREMISE_SUB2A : PREMISE_OK;
 }
 
 // v += rows s = 0, 1, ..., S-1 of a split-row array (component c of particle

@@ -698,6 +698,13 @@ sd_status sd_mean_vector(int64_t n, const double* v, double* out, void* stream)
     return SD_OK;
 }
 
+sd_status sd_premise_counts(int64_t* sub2a, int64_t* coincident, int32_t reset, void* stream)
+{
+    hipError_t e = premise_counts(sub2a, coincident, reset != 0, (hipStream_t)stream);
+    if (e != hipSuccess) return fail(SD_EDEVICE, "premise counts: %s", hipGetErrorString(e));
+    return SD_OK;
+}
+
 sd_status sd_set_kernel_config(int32_t precision, const sd_kernel_config* cfg)
 {
     sd_status st;

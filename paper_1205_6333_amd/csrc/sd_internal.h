@@ -129,6 +129,9 @@ hipError_t launch_pair_fold(const PairLaunch& L, int tensor, const float4* pos, 
                             hipStream_t st);
 
 // v_i = mu0 F_i + sum_s partial_s (fixed order).
+// Read the current device's counts of pairs with 0 < r < 2a and r = 0 met by
+// the product kernels (stream-ordered; synchronises st), zeroing them if reset.
+hipError_t premise_counts(int64_t* sub2a, int64_t* coincident, bool reset, hipStream_t st);
 hipError_t launch_merge_f32(const double* partial, int splits, int n, const float4* frc, double mu0,
                             double* vel, hipStream_t st);
 hipError_t launch_merge_f64(const double* partial, int splits, int n, const double4* frc,
