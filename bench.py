@@ -252,6 +252,7 @@ def run_timeloop(args, sd, W, dev):
         x = torch.tensor(x0, device=dev)
         vcm = []
         chunk = max(1, steps // 20)
+        sd.sd_premise_counts(reset=True)
 
         def go():
             done = 0
@@ -262,15 +263,22 @@ def run_timeloop(args, sd, W, dev):
                 done += k
                 vcm.append(sd.sd_mean_vector(vp))
         t = _sync_time(go)
-        res[prec] = (t, x.cpu().numpy(), torch.stack(vcm).cpu().numpy())
-    t32, x32, v32 = res[sd.SD_FP32_KAHAN]
-    t64, x64, v64 = res[sd.SD_FP64]
+        res[prec] = (t, x.cpu().numpy(), torch.stack(vcm).cpu().numpy(),
+                     sd.sd_premise_counts(reset=True))
+    t32, x32, v32, pc32 = res[sd.SD_FP32_KAHAN]
+    t64, x64, v64, _ = res[sd.SD_FP64]
     out.update({"value": steps / t32, "steps": steps, "ms_per_step": t32 * 1e3 / steps,
                 "g_pairs_per_s": float(n) * n * steps / t32 / 1e9,
                 "fp64_steps_per_s": steps / t64, "speedup_vs_fp64": t64 / t32,
                 "vcm_z_final": float(v32[-1, 2]), "vcm_z_final_fp64": float(v64[-1, 2]),
                 "vcm_drift_vs_fp64_max": float(np.abs(v32 - v64).max()),
-                "x_final_vs_fp64_max_abs": float(np.abs(x32 - x64).max())})
+                "x_final_vs_fp64_max_abs": float(np.abs(x32 - x64).max()),
+                # overlapping pairs (r < 2a) met per step, on average over the run
+                "overlapping_pairs_per_step": pc32[0] / steps,
+                # v_cm after every chunk of steps: FP32-comp z, FP64 z, largest
+                # component difference
+                "vcm_series": [[min(steps, (k + 1) * chunk), float(v32[k, 2]), float(v64[k, 2]),
+                                float(np.abs(v32[k] - v64[k]).max())] for k in range(len(v32))]})
     return out
 
 

@@ -21,7 +21,11 @@
  *  - Errors are returned as sd_status; the library never aborts.  A failed
  *    argument check enqueues nothing.  sd_last_error() gives a message for the
  *    last failure of the calling thread.  NaN/Inf inputs are not checked; they
- *    propagate into the results.
+ *    propagate into the results (every row of a product sums a term of every
+ *    particle, so one non-finite position or force makes every row
+ *    non-finite), and leave no state behind.  In a periodic box positions enter
+ *    as fixed-point records: a non-finite position becomes an unspecified
+ *    point of the box there.
  *  - Output arrays may not alias input arrays unless a parameter says so.
  *  - Layouts:
  *      "f32x4[n]"  n records of 4 floats  (x, y, z, w), 16-byte aligned, w ignored
@@ -69,7 +73,14 @@ typedef enum sd_precision {
     SD_FP32_KAHAN = 0,    /* FP32 pair evaluation, Kahan-compensated FP32
                              per-particle accumulation (the paper's "single
                              precision tensor, higher-precision accumulation",
-                             Sec. 3.2) */
+                             Sec. 3.2): terms summed in FP32 in blocks of
+                             sd_kernel_config.kahan_block, each block added
+                             with compensation; split rows added in FP64.
+                             The pair-symmetric kernel (variant 2) compensates
+                             the i side so; the terms it hands to j are summed
+                             in FP32 over at most 32 pairs, those sums in FP64
+                             over the i-block, rounded to FP32 once per i-block
+                             and j and added in FP64 */
     SD_FP64 = 1,          /* FP64 throughout */
     SD_FP32_PLAIN = 2     /* FP32 evaluation and plain FP32 accumulation */
 } sd_precision;
@@ -423,9 +434,8 @@ typedef struct sd_kernel_config {
                              compensated add (1 = per term, 2, 4, or 8 with
                              block >= 128; variant 2 also 16 or 32); 0 for
                              the other precisions.  Variant 2 sums the
-                             j side in FP32 over at most 32 terms per
-                             chunk before its FP64 fold, whatever the
-                             value */
+                             j side in FP32 over at most 32 terms before
+                             its FP64 sums, whatever the value */
 } sd_kernel_config;
 
 /* Force a configuration for a precision (NULL restores automatic choice). */

@@ -25,7 +25,8 @@ records (PER):
     for the lane's particles l = 0, 1:
       d = x_l - x_e (PER: the wrapped 32-bit difference, converted)
       r2 = d.d; near pairs (r2 < thr2, tested for every group of two steps
-      and masked to r2 = +inf, which makes the pair contribute zero) set NEAR
+      and masked to r2 = +inf, which makes the pair contribute zero) add
+      their lanes to NL and the chunk's bit to NF
       (the projections d.F of the group's first step are issued between
       the compare and the branch on its result, which hides the branch's
       wait for the compare)
@@ -212,6 +213,8 @@ def gen(tensor, per):
         E.op("s_waitcnt lgkmcnt(%d)" % (6 if (g < 7 and PREFETCH) else 0))
         dots(g, 0)
         E.op("s_cbranch_vccz SD_SKIP%d_%%=" % g)
+        # the lanes with a near pair in this group (VCC of the test)
+        E.op("s_or_b64 %[nl], %[nl], vcc")
         for u in range(2):
             for l in range(2):
                 r2 = R.R2[u][l]
@@ -219,7 +222,10 @@ def gen(tensor, per):
                 E.op("v_cmp_lt_f32 vcc, %s, %s" % (v(r2), v(th)), (r2, th))
                 E.op("s_nop 1")
                 E.op("v_cndmask_b32 %s, %s, %s, vcc" % (v(r2), v(r2), v(R.inf)))
-        E.op("s_mov_b32 %[nf], 1")
+        # the chunk's bit: chunk 8 - cnt of the tile
+        E.op("s_sub_u32 %[tmp], 8, %[cnt]")
+        E.op("s_lshl_b32 %[tmp], 1, %[tmp]")
+        E.op("s_or_b32 %[nf], %[nf], %[tmp]")
         E.op("SD_SKIP%d_%%=:" % g)
         # phase 2: the pair terms, step by step
         for u in range(2):

@@ -167,9 +167,33 @@ __device__ __forceinline__ void near_diff(const LaneF32& L, const float4 pj, int
 // on the rare FP64 near-pair branch only, by the evaluation of row min(i, j).
 __device__ unsigned long long g_premise[2];
 
+// Called by the lanes active at that point, each with the class of its pair
+// (PREMISE_OK for none): one atomic add per class and call, by one lane, for
+// the whole wave (a dense suspension meets thousands of such pairs per
+// product, and atomics on one address serialise).
 __device__ __forceinline__ void count_premise(int cls)
 {
-    if (cls != PREMISE_OK) atomicAdd(&g_premise[cls - 1], 1ull);
+    const uint64_t sub = __builtin_amdgcn_ballot_w64(cls == PREMISE_SUB2A);
+    const uint64_t co = __builtin_amdgcn_ballot_w64(cls == PREMISE_COINCIDENT);
+    if ((sub | co) == 0) return;
+    const uint64_t act = __builtin_amdgcn_ballot_w64(true);
+    if ((int)(threadIdx.x & 63) != __builtin_ctzll(act)) return;
+    if (sub) atomicAdd(&g_premise[0], (unsigned long long)__builtin_popcountll(sub));
+    if (co) atomicAdd(&g_premise[1], (unsigned long long)__builtin_popcountll(co));
+}
+
+// Per-lane counts, added for the wave with one atomic add per class (all
+// lanes of the wave call it).
+__device__ __forceinline__ void count_premise_lanes(uint32_t sub, uint32_t co)
+{
+    for (int off = 32; off > 0; off >>= 1) {
+        sub += __shfl_xor(sub, off);
+        co += __shfl_xor(co, off);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        if (sub) atomicAdd(&g_premise[0], (unsigned long long)sub);
+        if (co) atomicAdd(&g_premise[1], (unsigned long long)co);
+    }
 }
 
 // One pair (i, j) on the FP32 fast path.  pj/fj: position and force of j
@@ -226,7 +250,7 @@ __device__ __forceinline__ void pair_f32(LaneF32& L, const float4 pj, const floa
             near_diff<PER>(L, pj, jg, pc, x64, d0, d1, d2);
             const int cls = near_term<TENSOR>(pc, d0, d1, d2, (double)fj.x, (double)fj.y,
                                               (double)fj.z, L.n0, L.n1, L.n2);
-            if (L.i < jg) count_premise(cls);
+            count_premise(L.i < jg ? cls : PREMISE_OK);
         }
     }
 }
@@ -246,7 +270,7 @@ __device__ __forceinline__ void near_pair_lds(const LaneF32& L, const float4 pj,
     double n0 = slot[0], n1 = slot[stride], n2 = slot[2 * stride];
     const int cls =
         near_term<TENSOR>(pc, d0, d1, d2, (double)fj.x, (double)fj.y, (double)fj.z, n0, n1, n2);
-    if (L.i < jg) count_premise(cls);
+    count_premise(L.i < jg ? cls : PREMISE_OK);
     slot[0] = n0;
     slot[stride] = n1;
     slot[2 * stride] = n2;
@@ -531,11 +555,14 @@ k_pair_f32_smem(const float4* __restrict__ pos, const float4* __restrict__ frc,
 //
 // Near pairs.  A pair with r^2 below the near threshold (near contact,
 // overlap, coincident spheres) contributes nothing here, on either side: its
-// r^2 is replaced by +inf, so that rsq gives 0.  The work-group records the
-// block pair (I, J) in a flag matrix instead, and k_sym_fold_near evaluates
-// every pair of the flagged block pairs in FP64, one-sided (both orderings),
-// with the same FP32 threshold test, so that exactly the masked pairs are
-// added back.  The hot loop thus holds no FP64 code and no function call.
+// r^2 is replaced by +inf, so that rsq gives 0.  The wave records instead,
+// in a flag matrix over runs of SYM_RUN = 64 consecutive particles, every
+// pair of runs that holds one of its particles and one particle of the tile,
+// and k_sym_fold_near evaluates every pair of the flagged run pairs in FP64,
+// one-sided (both orderings), with the same FP32 threshold test, so that
+// exactly the masked pairs are added back.  The hot loop thus holds no FP64
+// code and no function call, and a near pair costs the fold 64 x 64 distance
+// tests, not a whole block pair.
 
 // Split schedule.  The i-blocks' virtual j ranges are cut alike, and the
 // launch orders its work-groups diagonal blocks first, then split 0 of every
@@ -552,6 +579,7 @@ SymShape sym_shape(int n, int block, int splits, int slots)
     sh.h = (sh.nb - 1) / 2;
     sh.extra = (sh.nb >= 2 && (sh.nb & 1) == 0) ? 1 : 0;
     sh.lmax = (sh.h + sh.extra) * block;
+    sh.nt = sh.lmax / SYM_TJ;
     const int tiles = sh.lmax / SYM_TJ;
     const int sp = splits < 1 ? 1 : splits;
     const int64_t big = std::max<int64_t>(1, (tiles + sp - 1) / sp);
@@ -588,6 +616,12 @@ SymShape sym_shape_of(const PairLaunch& L, int n)
     return sym_shape(n, L.block * L.ilp, L.jchunk, sym_slots(L.block, L.cus));
 }
 
+size_t sym_flags_bytes(const SymShape& sh, int block)
+{
+    const size_t rows = (size_t)sh.nb * (size_t)(block / SYM_RUN);
+    return (rows * (size_t)sh.nt + rows) * sizeof(uint4);
+}
+
 size_t sym_jpart_floats(const SymShape& sh) { return (size_t)3 * sh.nb * (size_t)sh.lmax; }
 
 size_t sym_jpart_offset(const PairLaunch& L, int64_t n)
@@ -605,8 +639,7 @@ size_t sym_flags_offset(const PairLaunch& L, int64_t n)
 
 size_t sym_workspace_bytes(const PairLaunch& L, int64_t n)
 {
-    const SymShape sh = sym_shape_of(L, (int)n);
-    return sym_flags_offset(L, n) + (size_t)sh.nb * (size_t)sh.nb * sizeof(uint32_t);
+    return sym_flags_offset(L, n) + sym_flags_bytes(sym_shape_of(L, (int)n), L.block * L.ilp);
 }
 
 // Compile-time loop: f(integral_constant<int, U>) for U = B .. E-1.
@@ -696,7 +729,7 @@ template <int TENSOR, int ACC, bool PER, int K0, int U, int ILP>
 __device__ __forceinline__ void sym_steps(SymLane (&L)[ILP], const float (&fi)[ILP][3],
                                           float (&y)[ILP][3], float& aj0, float& aj1, float& aj2,
                                           const float4* sp, const float4* sf,
-                                          const VConst& kc, bool& near)
+                                          const VConst& kc, uint64_t& near)
 {
     const float gamma = kc.gamma, m3g = kc.m3g, thr2 = kc.thr2;
     constexpr int KB = ACC > 0 ? ACC : 1;
@@ -726,8 +759,9 @@ __device__ __forceinline__ void sym_steps(SymLane (&L)[ILP], const float (&fi)[I
             rmin = (l == 0 && u == 0) ? r2[l][u] : fminf(rmin, r2[l][u]);
         }
     }
-    if (__builtin_amdgcn_ballot_w64(rmin < thr2) != 0) {   // rare
-        near = true;
+    const uint64_t nearb = __builtin_amdgcn_ballot_w64(rmin < thr2);
+    if (nearb != 0) {   // rare
+        near |= nearb;
 #pragma unroll
         for (int l = 0; l < ILP; ++l)
 #pragma unroll
@@ -828,7 +862,7 @@ __device__ __forceinline__ void sym_steps(SymLane (&L)[ILP], const float (&fi)[I
 template <int TENSOR, int ACC, int G, int ILP, bool PER>
 __device__ __forceinline__ void diag_group(SymLane (&L)[ILP], const int (&ig)[ILP],
                                            const float4 (&pjv)[G], const float4 (&fjv)[G],
-                                           int jg0, const VConst& kc, bool& near)
+                                           int jg0, const VConst& kc, uint64_t& near)
 {
     const float gamma = kc.gamma, m3g = kc.m3g, thr2 = kc.thr2;
     float pjx[G], pjy[G], pjz[G], fjx[G], fjy[G], fjz[G];
@@ -863,7 +897,7 @@ __device__ __forceinline__ void diag_group(SymLane (&L)[ILP], const int (&ig)[IL
                 other = other || (nr && jg0 + u != ig[l]);
                 r2[l][u] = nr ? __builtin_inff() : r2[l][u];
             }
-        if (__builtin_amdgcn_ballot_w64(other) != 0) near = true;
+        near |= __builtin_amdgcn_ballot_w64(other);
     }
 #pragma unroll
     for (int l = 0; l < ILP; ++l) {
@@ -935,14 +969,53 @@ struct SymWaves {
     static constexpr int value = BLOCK >= 256 ? 4 : 2;
 };
 
+// Near flags.  Row W = ib * RB + w (RB = B / SYM_RUN rows per i-block, w the
+// wave) holds one 16-byte entry per tile t of the block's virtual j range:
+// the lanes of wave w that met a near pair with that tile (64 bits: a lane
+// holds particles tid and tid + BLOCK) and the chunks of 16 j particles of the
+// tile they were met in (8 bits).  After the rows, one 16-byte entry per W:
+// the lanes that met a near pair within their own block (the diagonal
+// work-group) and the chunks of 16 particles of the block (32 bits).  Every call writes every entry it covers (zero if nothing was
+// met), so nothing is cleared and no earlier call's entries are ever read.
+template <int BLOCK, int ILP>
+__device__ __forceinline__ uint4* sym_flag_row(uint8_t* __restrict__ flags, const SymShape& sh,
+                                               int ib)
+{
+    constexpr int RB = BLOCK * ILP / SYM_RUN;
+    const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));   // wave-uniform
+    return (uint4*)flags + (size_t)(ib * RB + w) * (size_t)sh.nt;
+}
+
+__device__ __forceinline__ void sym_flag_tile(uint4* __restrict__ frow, int t, uint64_t lanes,
+                                              uint32_t chunks)
+{
+    if ((threadIdx.x & 63) == 0) {
+        uint32_t* e = (uint32_t*)(frow + t);
+        *(uint2*)e = make_uint2((uint32_t)lanes, (uint32_t)(lanes >> 32));
+        e[2] = chunks;
+    }
+}
+
+template <int BLOCK, int ILP>
+__device__ __forceinline__ void sym_flag_diag(uint8_t* __restrict__ flags, const SymShape& sh,
+                                              int ib, uint64_t lanes, uint32_t chunks)
+{
+    constexpr int RB = BLOCK * ILP / SYM_RUN;
+    const size_t rows = (size_t)sh.nb * RB;
+    uint4* d = (uint4*)flags + rows * (size_t)sh.nt;
+    if ((threadIdx.x & 63) == 0)
+        d[ib * RB + (int)(threadIdx.x >> 6)] =
+            make_uint4((uint32_t)lanes, (uint32_t)(lanes >> 32), chunks, 0u);
+}
+
 // ILP particles per lane (ILP 2: the i-block of BLOCK * ILP particles has
 // particle tid and tid + BLOCK in lane tid), groups of U steps.
-// flags: nb x nb block-pair matrix of near pairs (see k_sym_fold_near).
+// flags: near flags per wave and tile (see sym_flag_row).
 template <int TENSOR, int ACC, int BLOCK, int ILP, bool PER>
 __global__ void __launch_bounds__(BLOCK, SymWaves<BLOCK>::value)
 k_pair_f32_sym(const float4* __restrict__ pos, const float4* __restrict__ frc, int n, SymShape sh,
                PairConst pc, double* __restrict__ partial, float* __restrict__ jpart,
-               uint32_t* __restrict__ flags)
+               uint8_t* __restrict__ flags)
 {
     constexpr int B = BLOCK * ILP;   // particles per block
     constexpr int U = ILP == 1 ? 8 : 4;
@@ -971,13 +1044,14 @@ k_pair_f32_sym(const float4* __restrict__ pos, const float4* __restrict__ frc, i
     const VConst kc = vconst(pc);
     const float4 far_j4 = make_float4(far_j<PER>(), far_j<PER>(), far_j<PER>(), 0.0f);
     const float4 zero4 = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-    bool near = false;
+    uint64_t near = 0;
 
     if (diag) {
         // the i-block with itself: every ordered pair, one-sided, in groups of
         // four (compensation at least every four terms)
         constexpr int ACC_D = ACC > 4 ? 4 : ACC;
         constexpr int G = 4;
+        uint32_t dch = 0;   // chunks of 16 j of the block with a near pair
         const int jt = ib * B;
         int ig[ILP];
 #pragma unroll
@@ -1001,9 +1075,14 @@ k_pair_f32_sym(const float4* __restrict__ pos, const float4* __restrict__ frc, i
                 pj[u] = s_pos[k + u];
                 fj[u] = s_frc[k + u];
             }
-            diag_group<TENSOR, ACC_D, G, ILP, PER>(L, ig, pj, fj, jt + k, kc, near);
+            uint64_t nd = 0;
+            diag_group<TENSOR, ACC_D, G, ILP, PER>(L, ig, pj, fj, jt + k, kc, nd);
+            if (nd != 0) {
+                near |= nd;
+                dch |= 1u << (k / 16);
+            }
         }
-        if (near && (tid & 63) == 0) flags[(size_t)ib * sh.nb + ib] = 1u;
+        sym_flag_diag<BLOCK, ILP>(flags, sh, ib, near, dch);
         sym_lanes_store<ILP, BLOCK>(L, n, ib, s, pc.alpha_sum, partial);
         return;
     }
@@ -1027,6 +1106,7 @@ k_pair_f32_sym(const float4* __restrict__ pos, const float4* __restrict__ frc, i
     const int lI = (sh.h + ((sh.extra && ib < half) ? 1 : 0)) * B;
     const int pbeg = sh.off[s] * SYM_TJ;
     const int pend = min(lI, sh.off[s + 1] * SYM_TJ);
+    uint4* const frow = sym_flag_row<BLOCK, ILP>(flags, sh, ib);
     // block J and first particle of the tile at virtual position pt
     auto tile_block = [&](int pt) { return (ib + 1 + pt / B) % sh.nb; };
     // this thread's records of the tile at pt: element e of record r is
@@ -1072,28 +1152,28 @@ k_pair_f32_sym(const float4* __restrict__ pos, const float4* __restrict__ frc, i
     for (int pt = pbeg, buf = 0; pt < pend; pt += SYM_TJ, buf ^= 1) {
         const bool more = pt + SYM_TJ < pend;
         if (more) tile_load(pt + SYM_TJ, rec);   // consumed after the chunk loop
+        uint32_t nch = 0;   // chunks of the tile with a near pair
 #pragma unroll 1
         for (int c = 0; c < SYM_TJ / 16; ++c) {
             float aj0, aj1, aj2;
             const float4* sp = s_pos + buf * TS + c * 32 + q;
             const float4* sf = s_frc + buf * TS + c * 32 + q;
+            uint64_t nc = 0;
             StaticFor<0, 16 / U>::run([&](auto g_c) {
                 constexpr int K0 = decltype(g_c)::value * U;
-                sym_steps<TENSOR, ACC, PER, K0, U, ILP>(L, fi, y, aj0, aj1, aj2, sp, sf, kc, near);
+                sym_steps<TENSOR, ACC, PER, K0, U, ILP>(L, fi, y, aj0, aj1, aj2, sp, sf, kc, nc);
             });
+            if (nc != 0) {
+                near |= nc;
+                nch |= 1u << c;
+            }
             s_jacc[(0 * ROWS + row) * SYM_TJ + c * 16 + q] = aj0;
             s_jacc[(1 * ROWS + row) * SYM_TJ + c * 16 + q] = aj1;
             s_jacc[(2 * ROWS + row) * SYM_TJ + c * 16 + q] = aj2;
         }
         if (more) tile_store(buf ^ 1, rec);
-        if (near) {
-            const int J = tile_block(pt);
-            if ((tid & 63) == 0) {
-                flags[(size_t)ib * sh.nb + J] = 1u;
-                flags[(size_t)J * sh.nb + ib] = 1u;
-            }
-            near = false;
-        }
+        sym_flag_tile(frow, pt / SYM_TJ, near, nch);
+        near = 0;
         __syncthreads();   // the tile's j-side sums are complete, the next tile is staged
         sym_tile_rows<BLOCK>(s_jacc, jpart, sh, ib, pt);
         __syncthreads();   // s_jacc is free for the next tile
@@ -1111,7 +1191,7 @@ template <int TENSOR, int ACC, bool PER>
 __global__ void __launch_bounds__(256, 4)
 k_pair_f32_sym_asm(const float4* __restrict__ pos, const float4* __restrict__ frc, int n,
                    SymShape sh, PairConst pc, double* __restrict__ partial,
-                   float* __restrict__ jpart, uint32_t* __restrict__ flags)
+                   float* __restrict__ jpart, uint8_t* __restrict__ flags)
 {
     constexpr int BLOCK = 256, ILP = 2, B = 512, ROWS = BLOCK / 16;
     constexpr int TS = 2 * SYM_TJ;     // floats of one doubled array of a tile
@@ -1134,10 +1214,11 @@ k_pair_f32_sym_asm(const float4* __restrict__ pos, const float4* __restrict__ fr
     SymLane L[ILP];
     sym_lanes_init<ILP, BLOCK, PER>(L, pos, n, ib);
     const VConst kc = vconst(pc);
-    bool near = false;
+    uint64_t near = 0;
 
     if (diag) {
         constexpr int G = 4;
+        uint32_t dch = 0;   // chunks of 16 j of the block with a near pair
         const int jt = ib * B;
         int ig[ILP];
 #pragma unroll
@@ -1168,9 +1249,14 @@ k_pair_f32_sym_asm(const float4* __restrict__ pos, const float4* __restrict__ fr
                 fj[u] = make_float4(s_soa[3 * B + k + u], s_soa[4 * B + k + u],
                                     s_soa[5 * B + k + u], 0.0f);
             }
-            diag_group<TENSOR, 4, G, ILP, PER>(L, ig, pj, fj, jt + k, kc, near);
+            uint64_t nd = 0;
+            diag_group<TENSOR, 4, G, ILP, PER>(L, ig, pj, fj, jt + k, kc, nd);
+            if (nd != 0) {
+                near |= nd;
+                dch |= 1u << (k / 16);
+            }
         }
-        if (near && (tid & 63) == 0) flags[(size_t)ib * sh.nb + ib] = 1u;
+        sym_flag_diag<BLOCK, ILP>(flags, sh, ib, near, dch);
         sym_lanes_store<ILP, BLOCK>(L, n, ib, s, pc.alpha_sum, partial);
         return;
     }
@@ -1197,13 +1283,15 @@ k_pair_f32_sym_asm(const float4* __restrict__ pos, const float4* __restrict__ fr
     float n0x = 0.0f, n0y = 0.0f, n0z = 0.0f, n1x = 0.0f, n1y = 0.0f, n1z = 0.0f;   // -compensation
     float k_gamma = kc.gamma, k_m3g = kc.m3g, k_thr2 = kc.thr2, k_inf = __builtin_inff();
     asm volatile("" : "+v"(k_inf));
-    uint32_t nearf = 0;
+    uint64_t nearl = 0;   // lanes that met a near pair in the tile
+    uint32_t nearf = 0;   // chunks of the tile they were met in
     const int q = tid & 15;
     const int row = tid >> 4;
     const int half = sh.nb >> 1;
     const int lI = (sh.h + ((sh.extra && ib < half) ? 1 : 0)) * B;
     const int pbeg = sh.off[s] * SYM_TJ;
     const int pend = min(lI, sh.off[s + 1] * SYM_TJ);
+    uint4* const frow = sym_flag_row<BLOCK, ILP>(flags, sh, ib);
     auto tile_block = [&](int pt) { return (ib + 1 + pt / B) % sh.nb; };
     // this thread's record of the tile at pt: position (tid < SYM_TJ) or force
     // of particle jt + tid mod SYM_TJ
@@ -1257,7 +1345,7 @@ k_pair_f32_sym_asm(const float4* __restrict__ pos, const float4* __restrict__ fr
                    [f0z] "+" SD_SYM_R_FI0z(f0z), [f1x] "+" SD_SYM_R_FI1x(f1x),                 \
                    [f1y] "+" SD_SYM_R_FI1y(f1y), [f1z] "+" SD_SYM_R_FI1z(f1z),                 \
                    [adr] "+" SD_SYM_R_ADDR(addr), [jadr] "+" SD_SYM_R_JADDR(jaddr),            \
-                   [nf] "+s"(nearf), [cnt] "=&s"(cnt), [tmp] "=&s"(stmp)                       \
+                   [nf] "+s"(nearf), [nl] "+s"(nearl), [cnt] "=&s"(cnt), [tmp] "=&s"(stmp)     \
                  : [gam] SD_SYM_R_GAMMA(k_gamma), [thr] SD_SYM_R_THR2(k_thr2),                 \
                    [thro] SD_SYM_R_THR2O(k_thr2), [inf] SD_SYM_R_INF(k_inf),                   \
                    [m3g] SD_SYM_R_M3G(k_m3g), [kmask] "s"(kmask)                               \
@@ -1275,14 +1363,9 @@ k_pair_f32_sym_asm(const float4* __restrict__ pos, const float4* __restrict__ fr
             tile_store(buf ^ 1, rec);
             if (pt + 2 * SYM_TJ < pend) rec = tile_load(pt + 2 * SYM_TJ);
         }
-        if (nearf) {
-            const int J = tile_block(pt);
-            if ((tid & 63) == 0) {
-                flags[(size_t)ib * sh.nb + J] = 1u;
-                flags[(size_t)J * sh.nb + ib] = 1u;
-            }
-            nearf = 0;
-        }
+        sym_flag_tile(frow, pt / SYM_TJ, nearl, nearf);
+        nearl = 0;
+        nearf = 0;
         __syncthreads();   // the tile's j-side sums are complete, the next tile is staged
         sym_tile_rows<BLOCK>(s_jacc, jpart, sh, ib, pt);
         __syncthreads();   // s_jacc is free for the next tile
@@ -1328,26 +1411,32 @@ __device__ __forceinline__ void near_diff_v(float xi, float yi, float zi, int i,
     }
 }
 
-// Last split row of variant 2, one work-group of B threads per block J
-// (thread o: particle q = J B + o):
+// Last split row of variant 2, one wave per run S of SYM_RUN particles
+// (lane: particle q = S SYM_RUN + lane, at offset o of its block J):
 //  * the j side: the FP32 partials of the blocks I that took block J,
 //    added in FP64 in a fixed order (I = J - 1, J - 2, ..., then the
 //    antipode), times alpha_sum;
-//  * the near pairs: for every block K flagged with J, every pair (q, j in K)
-//    below the FP32 near threshold (the test of the pair kernel, so exactly
-//    the masked pairs), j != q, evaluated in FP64 (near_term), K ascending,
-//    j ascending.  The flags read are cleared for the next product.
+//  * the near pairs: every candidate the near flags name (see below) below
+//    the FP32 near threshold (the test of the pair kernel, so exactly the
+//    masked pairs), j != q, evaluated in FP64 (near_term) in the order of
+//    the candidate list.
 template <int TENSOR, bool PER>
-__global__ void __launch_bounds__(512)
+__global__ void __launch_bounds__(SYM_RUN)
 k_sym_fold_near(const float* __restrict__ jpart, const float4* __restrict__ pos,
                 const float4* __restrict__ frc, const double* __restrict__ x64, int n, int B,
-                SymShape sh, PairConst pc, uint32_t* __restrict__ flags, double* __restrict__ out)
+                int wpb, SymShape sh, PairConst pc, const uint8_t* __restrict__ flags,
+                double* __restrict__ out)
 {
-    __shared__ float4 s_pos[512];
-    __shared__ float4 s_frc[512];
-    __shared__ uint32_t s_fl[512];
-    const int J = blockIdx.x, o = threadIdx.x;
-    const int q = J * B + o;
+    constexpr int FOLD_CAP = 256;   // candidates listed before their records are loaded
+    __shared__ float4 s_pos[FOLD_CAP];
+    __shared__ float4 s_frc[FOLD_CAP];
+    __shared__ double s_x64[3 * FOLD_CAP];   // FP64 positions when x64 is given
+    __shared__ int s_idx[FOLD_CAP];
+    // one wave per run S of SYM_RUN particles; particle q at offset o of block J
+    const int S = blockIdx.x, lane = threadIdx.x;
+    const int q = S * SYM_RUN + lane;
+    const int J = (S * SYM_RUN) / B;
+    const int o = q - J * B;
     const int nb = sh.nb, half = nb >> 1;
     const size_t cs = (size_t)nb * (size_t)sh.lmax;
     double v0 = 0.0, v1 = 0.0, v2 = 0.0;
@@ -1390,50 +1479,154 @@ k_sym_fold_near(const float* __restrict__ jpart, const float4* __restrict__ pos,
     v0 *= pc.alpha_sum;
     v1 *= pc.alpha_sum;
     v2 *= pc.alpha_sum;
+    // near pairs of q.  The flags name candidate particles; they are listed in
+    // LDS in a fixed order (the diagonal block, the flagged chunks of the tiles
+    // in the row of q's wave: q's block as i-block, then the flagged lanes of
+    // the waves of preceding blocks whose entry for q's tile names a chunk of
+    // q's run: q's block as j-block), their records are loaded together once
+    // FOLD_CAP are listed or the list ends, and every q tests every listed
+    // candidate (the FP32 threshold test again, then FP64).  A pair of
+    // different blocks lies in the virtual range of exactly one of the two,
+    // and each source lists a particle once, so every near pair is found once.
     const float thr2 = pc.thr2_f;
     float xq = far_i<PER>(), yq = far_i<PER>(), zq = far_i<PER>();
+    double xq64[3] = { 0.0, 0.0, 0.0 };
     if (q < n) {
         const float4 p = pos[q];
         xq = p.x;
         yq = p.y;
         zq = p.z;
-    }
-    for (int K0 = 0; K0 < nb; K0 += B) {
-        __syncthreads();
-        uint32_t f = 0;
-        if (K0 + o < nb) {
-            f = flags[(size_t)J * nb + K0 + o];
-            if (f) flags[(size_t)J * nb + K0 + o] = 0u;
+        if (x64) {
+            xq64[0] = x64[3 * (size_t)q];
+            xq64[1] = x64[3 * (size_t)q + 1];
+            xq64[2] = x64[3 * (size_t)q + 2];
         }
-        s_fl[o] = f;
+    }
+    int cnt = 0;   // listed candidates (the same in every lane)
+    uint32_t psub = 0, pco = 0;   // this lane's pairs against the premise r >= 2a
+    auto flush = [&]() {
         __syncthreads();
-        const int kend = min(nb - K0, B);
-        for (int kk = 0; kk < kend; ++kk) {
-            if (s_fl[kk] == 0u) continue;
-            const int jt = (K0 + kk) * B;
-            __syncthreads();
-            s_pos[o] = jt + o < n ? pos[jt + o] : make_float4(far_j<PER>(), far_j<PER>(),
-                                                              far_j<PER>(), 0.0f);
-            s_frc[o] = jt + o < n ? frc[jt + o] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-            __syncthreads();
-            for (int e = 0; e < B; ++e) {
+        for (int k = lane; k < cnt; k += SYM_RUN) {
+            const int jg = s_idx[k];
+            const bool in = jg < n;
+            s_pos[k] = in ? pos[jg] : make_float4(far_j<PER>(), far_j<PER>(), far_j<PER>(), 0.0f);
+            s_frc[k] = in ? frc[jg] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+            if (x64) {
+                s_x64[3 * k] = in ? x64[3 * (size_t)jg] : 0.0;
+                s_x64[3 * k + 1] = in ? x64[3 * (size_t)jg + 1] : 0.0;
+                s_x64[3 * k + 2] = in ? x64[3 * (size_t)jg + 2] : 0.0;
+            }
+        }
+        __syncthreads();
+        // the FP32 test for groups of 8 candidates, then the pairs it found
+        // in ascending order
+        for (int e0 = 0; e0 < cnt; e0 += 8) {
+            uint32_t nm = 0;
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                if (e0 + u < cnt) {
+                    const float4 pj = s_pos[e0 + u];
+                    const float dx = pdiff<PER>(xq, pj.x);
+                    const float dy = pdiff<PER>(yq, pj.y);
+                    const float dz = pdiff<PER>(zq, pj.z);
+                    if (fmaf(dx, dx, fmaf(dy, dy, dz * dz)) < thr2) nm |= 1u << u;
+                }
+            }
+            for (; nm != 0u; nm &= nm - 1u) {
+                const int e = e0 + __builtin_ctz(nm);
                 const float4 pj = s_pos[e];
-                const float dx = pdiff<PER>(xq, pj.x);
-                const float dy = pdiff<PER>(yq, pj.y);
-                const float dz = pdiff<PER>(zq, pj.z);
-                const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
-                const int jg = jt + e;
-                if (r2 < thr2 && jg != q && q < n && jg < n) {
+                const int jg = s_idx[e];
+                if (jg != q && q < n && jg < n) {
                     const float4 fj = s_frc[e];
                     double d0, d1, d2;
-                    near_diff_v<PER>(xq, yq, zq, q, pj, jg, pc, x64, d0, d1, d2);
-                    const int cls = near_term<TENSOR>(pc, d0, d1, d2, (double)fj.x,
-                                                      (double)fj.y, (double)fj.z, v0, v1, v2);
-                    if (q < jg) count_premise(cls);
+                    if (x64) {   // the FP64 positions, staged
+                        d0 = xq64[0] - s_x64[3 * e];
+                        d1 = xq64[1] - s_x64[3 * e + 1];
+                        d2 = xq64[2] - s_x64[3 * e + 2];
+                        if (PER) nearest_image_d(pc, d0, d1, d2);
+                    } else {
+                        near_diff_v<PER>(xq, yq, zq, q, pj, jg, pc, nullptr, d0, d1, d2);
+                    }
+                    const int cls = near_term<TENSOR>(pc, d0, d1, d2, (double)fj.x, (double)fj.y,
+                                                      (double)fj.z, v0, v1, v2);
+                    if (q < jg) {
+                        psub += cls == PREMISE_SUB2A;
+                        pco += cls == PREMISE_COINCIDENT;
+                    }
                 }
             }
         }
+        __syncthreads();
+        cnt = 0;
+    };
+    auto add_range = [&](int j0, int len) {   // particles j0 .. j0 + len - 1, len <= 64
+        if (cnt + len > FOLD_CAP) flush();
+        if (lane < len) s_idx[cnt + lane] = j0 + lane;
+        cnt += len;
+    };
+    const int RB = B / SYM_RUN;          // runs (= flag rows) per block
+    const int r = S - J * RB;            // q's run within its block
+    const int w = r % wpb;               // the wave that holds it
+    const int ilp = RB / wpb;
+    const int nt = sh.nt;
+    const size_t rows = (size_t)nb * RB;
+    const int TB = B / SYM_TJ;           // tiles per block
+    const uint4* ftile = (const uint4*)flags;
+    const uint4* fdiag = ftile + rows * (size_t)nt;
+    for (uint32_t ch = fdiag[J * RB + w].z; ch != 0u; ch &= ch - 1u)
+        add_range(J * B + 16 * __builtin_ctz(ch), 16);
+    const int ntJ = (sh.h + ((sh.extra && J < half) ? 1 : 0)) * TB;
+    const uint4* frow = ftile + (size_t)(J * RB + w) * nt;
+    // (the entries are read by all lanes at once and handed out with readlane:
+    // a load per flagged entry would put a memory latency in the chain)
+    for (int t0 = 0; t0 < ntJ; t0 += 64) {
+        const uint32_t chl = t0 + lane < ntJ ? frow[t0 + lane].z : 0u;
+        uint64_t m = __builtin_amdgcn_ballot_w64(chl != 0u);
+        while (m) {
+            const int k = __builtin_ctzll(m);
+            m &= m - 1;
+            const int pt = (t0 + k) * SYM_TJ;
+            const int jt = ((J + 1 + pt / B) % nb) * B + pt % B;
+            for (uint32_t ch = __builtin_amdgcn_readlane(chl, k); ch != 0u; ch &= ch - 1u)
+                add_range(jt + 16 * __builtin_ctz(ch), 16);
+        }
     }
+    // q's block J is block d of the virtual range of I = J - d (d = 1 .. h),
+    // and block h + 1 of I = J + nb / 2 when nb is even and I < nb / 2; q's
+    // run covers chunks c0 .. c0 + 3 of its tile tq
+    const int tq = (r * SYM_RUN) / SYM_TJ;
+    const uint32_t rch = 0xFu << (((r * SYM_RUN) % SYM_TJ) / 16);
+    const int Ie = (J + half) % nb;
+    const int dmax = sh.h + ((sh.extra && Ie < half) ? 1 : 0);
+    for (int c0 = 0; c0 < dmax * wpb; c0 += 64) {
+        uint4 ev = make_uint4(0u, 0u, 0u, 0u);
+        const int c = c0 + lane;          // c = (d - 1) wpb + w'
+        if (c < dmax * wpb) {
+            const int d = c / wpb + 1, wp = c % wpb;
+            const int I = (J - d + nb) % nb;
+            ev = ftile[(size_t)(I * RB + wp) * nt + (size_t)((d - 1) * TB + tq)];
+        }
+        uint64_t m = __builtin_amdgcn_ballot_w64((ev.z & rch) != 0u);
+        while (m) {
+            const int k = __builtin_ctzll(m);
+            m &= m - 1;
+            const int cc = c0 + k;
+            const int d = cc / wpb + 1, wp = cc % wpb;
+            const int I = (J - d + nb) % nb;
+            const uint64_t lanes = ((uint64_t)(uint32_t)__builtin_amdgcn_readlane(ev.y, k) << 32) |
+                                   (uint32_t)__builtin_amdgcn_readlane(ev.x, k);
+            // lane k of wave w' holds particles I B + l BLOCK + 64 w' + k
+            const int add = __builtin_popcountll(lanes) * ilp;
+            if (cnt + add > FOLD_CAP) flush();
+            const int at = __builtin_popcountll(lanes & ((1ull << lane) - 1ull));
+            if ((lanes >> lane) & 1)
+                for (int l = 0; l < ilp; ++l)
+                    s_idx[cnt + at * ilp + l] = I * B + l * (wpb * SYM_RUN) + wp * SYM_RUN + lane;
+            cnt += add;
+        }
+    }
+    if (cnt > 0) flush();
+    count_premise_lanes(psub, pco);
     if (q < n) {
         out[q] = v0;
         out[(size_t)n + q] = v1;
@@ -1514,7 +1707,7 @@ k_pair_f64_lds(const double4* __restrict__ pos, const double4* __restrict__ frc,
             v2 = fma(A, fj.z, fma(sB, dz, v2));
             if (nr && (jt + k) != i && i < n && (jt + k) < n) {
                 const int cls = near_term<TENSOR>(pc, dx, dy, dz, fj.x, fj.y, fj.z, n0, n1, n2);
-                if (i < jt + k) count_premise(cls);
+                count_premise(i < jt + k ? cls : PREMISE_OK);
             }
         }
     }
@@ -1576,7 +1769,7 @@ static hipError_t launch_f32_sym(const PairLaunch& L, const float4* pos, const f
 {
     const SymShape sh = sym_shape_of(L, n);
     float* jpart = (float*)((char*)partial + sym_jpart_offset(L, n));
-    uint32_t* flags = (uint32_t*)((char*)partial + sym_flags_offset(L, n));
+    uint8_t* flags = (uint8_t*)partial + sym_flags_offset(L, n);
     dim3 grid(sh.nb * sh.isplits + sh.nb), block(BLOCK);
     if constexpr (ACC == 16 || ACC == 32) {
         static_assert(BLOCK == 256 && ILP == 2, "Kahan blocks of 16 or 32: the assembly shape");
@@ -1605,11 +1798,13 @@ hipError_t launch_pair_fold(const PairLaunch& L, int tensor, const float4* pos, 
     if (L.variant != 2) return hipSuccess;
     const SymShape sh = sym_shape_of(L, n);
     const float* jpart = (const float*)((const char*)partial + sym_jpart_offset(L, n));
-    uint32_t* flags = (uint32_t*)((char*)partial + sym_flags_offset(L, n));
+    uint8_t* flags = (uint8_t*)partial + sym_flags_offset(L, n);
     double* out = partial + (size_t)(sh.isplits + 1) * 3 * (size_t)n;
     const int B = L.block * L.ilp;
     const bool per = pc.box > 0.0;
-#define SD_FOLD(T, P)                                                                              hipLaunchKernelGGL((k_sym_fold_near<T, P>), dim3(sh.nb), dim3(B), 0, st, jpart, pos, frc,                         x64, n, B, sh, pc, flags, out)
+#define SD_FOLD(T, P)                                                                      \
+    hipLaunchKernelGGL((k_sym_fold_near<T, P>), dim3(sh.nb * (B / SYM_RUN)), dim3(SYM_RUN), 0, \
+                       st, jpart, pos, frc, x64, n, B, L.block / 64, sh, pc, flags, out)
     if (tensor == T_OSEEN) {
         if (per) SD_FOLD(T_OSEEN, true); else SD_FOLD(T_OSEEN, false);
     } else {

@@ -95,8 +95,11 @@ PairLaunch shape_pair_launch(int n, int variant, int block, int splits, int ilp,
 // result).
 constexpr int SYM_TJ = 128;          // j tile of the symmetric kernel
 constexpr int SYM_MAX_SPLITS = 96;
+// The particles of one wave and lane slot: SYM_RUN consecutive particles.
+constexpr int SYM_RUN = 64;
 struct SymShape {
     int nb, h, extra, lmax, isplits;
+    int nt;   // tiles of SYM_TJ in the longest virtual j range (lmax / SYM_TJ)
     int off[SYM_MAX_SPLITS + 1];
 };
 // splits: the largest split covers about 1/splits of the range; slots:
@@ -109,6 +112,8 @@ size_t sym_jpart_floats(const SymShape& sh);
 size_t sym_jpart_offset(const PairLaunch& L, int64_t n);
 size_t sym_flags_offset(const PairLaunch& L, int64_t n);
 size_t sym_workspace_bytes(const PairLaunch& L, int64_t n);
+// near flags: (nb * block / SYM_RUN) x nt bytes, then nb * block / SYM_RUN
+size_t sym_flags_bytes(const SymShape& sh, int block);
 
 // Pair kernels: partial[(s*3 + k)*n + i] = sum over split s of the pair terms
 // (self excluded), FP64 output.

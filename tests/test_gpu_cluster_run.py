@@ -150,3 +150,31 @@ def test_cluster_run_random_cluster_64(sd, orc):
         err = np.abs(st[0, 0] + st[0, 1] - xr).max() / np.abs(xr - x0).max()
         print("n=64 acc=%d pos=%d err=%.3e" % (acc, pos, err))
         assert err <= tol
+
+
+def test_four_sphere_plane_symmetry_by_accumulation_precision(sd):
+    """Sec. 4 (the figure of particle 1's deviation from the xz-plane, dt =
+    0.001 tau_s): with the hydrodynamic interactions accumulated in
+    double-single (or FP64), particle 1 stays in the plane exactly, y_1 = 0 in
+    every frame bit for bit, whatever the precision of the positions; with
+    single-precision accumulation and double-single positions y_1 leaves 0
+    and its deviation grows over the run."""
+    x0, f = W.four_sphere_tetrahedron()
+    steps, stride, dt = 300000, 1000, 0.001
+    specs = [dict(acc=2, pos=1, dt=dt, steps=steps, stride=stride),   # DS HI, DS positions
+             dict(acc=2, pos=2, dt=dt, steps=steps, stride=stride),   # DS HI, FP64 positions
+             dict(acc=3, pos=1, dt=dt, steps=steps, stride=stride),   # FP64 HI, DS positions
+             dict(acc=0, pos=1, dt=dt, steps=steps, stride=stride)]   # single HI, DS positions
+    st, tr = _run(sd, x0, f, specs)
+    nf = steps // stride
+    y1 = tr[:, 0, 1].reshape(len(specs), nf)
+    for r in range(3):
+        assert np.all(y1[r] == 0.0), (specs[r], np.abs(y1[r]).max())
+        assert st[r, :, 0, 1].tolist() == [0.0, 0.0]       # hi and lo parts of y_1
+    dev = np.abs(y1[3])
+    print("single-HI |y1|: first nonzero frame %d, max %.3e, last %.3e"
+          % (int(np.argmax(dev > 0)), dev.max(), dev[-1]))
+    assert dev.max() > 0.0
+    # the deviation grows: the last tenth of the run is above the first tenth
+    k = nf // 10
+    assert dev[-k:].max() > dev[:k].max()
