@@ -66,10 +66,10 @@ SMALL_N = 16384             # the second size of the single-product benchmark
 # followed by sym_chunk_asm.h) and launch configuration the counters were taken
 # with; otherwise reported as null.
 KERNEL_SOURCES = ("mobility.hip", "sym_chunk_asm.h")
-PMC_TRAFFIC = {"source_sha1": "3202888228eef94652fcc564b6e71d2ab495a07e",
+PMC_TRAFFIC = {"source_sha1": "b3b15ec738a11c26c719143ca062ab21f1579543",
                "n": 65536,
-               "config": {"variant": 2, "block": 256, "splits": 32, "ilp": 2, "kahan_block": 8},
-               "fetch_kib": 59207.3, "write_kib": 449575.0, "fetch_scale": 2.0, "write_scale": 1.0}
+               "config": {"variant": 2, "block": 256, "splits": 32, "ilp": 2, "kahan_block": 32},
+               "fetch_kib": 16173.0, "write_kib": 121567.0, "fetch_scale": 2.0, "write_scale": 1.0}
 
 
 def _measured_traffic(n, cfg):
@@ -92,10 +92,10 @@ def _measured_traffic(n, cfg):
 # VALU wave instructions of one product-kernel launch (rocprofv3 SQ_INSTS_VALU,
 # profiles/pair_kernel_f32_n65536_valu_counters.md), same validity rule.
 PMC_VALU = {"source_sha1": PMC_TRAFFIC["source_sha1"], "n": 65536,
-            "config": PMC_TRAFFIC["config"], "valu_wave_instr": 1204900352,
+            "config": PMC_TRAFFIC["config"], "valu_wave_instr": 1189680640,
             # SQ_INSTS_VALU_{ADD,MUL,FMA,TRANS}_F32 per dispatch (wave instructions)
-            "add_f32": 190021632, "mul_f32": 319455232, "fma_f32": 622198784,
-            "trans_f32": 33849344}
+            "add_f32": 158810112, "mul_f32": 319508480, "fma_f32": 622198784,
+            "trans_f32": 33902592}
 
 
 def _measured_valu(n, cfg):
