@@ -381,9 +381,11 @@ sd_status sd_cluster_run(const sd_params* p, int64_t n, int32_t runs, const sd_c
  * path; they characterise the j-data paths the product kernel chooses from). */
 typedef enum sd_mb_kernel {
     SD_MB_NAIVE = 0,        /* every thread reads its N elements from global memory */
-    SD_MB_SMALLTILING = 1,  /* the first wave (64 threads) fills an LDS tile of 64
-                               elements; the work-group of 128 threads reads it */
-    SD_MB_TILING = 2        /* the whole work-group fills a tile of 128 elements */
+    SD_MB_SMALLTILING = 1,  /* the first wave (64 threads) fills LDS tiles of 64
+                               elements; the work-group of 128 threads reads them
+                               (two buffers: the next tile is fetched while the
+                               current one is summed) */
+    SD_MB_TILING = 2        /* the whole work-group fills tiles of 128 elements */
 } sd_mb_kernel;
 
 typedef enum sd_mb_map {

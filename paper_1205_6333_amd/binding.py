@@ -14,7 +14,9 @@ import os
 from typing import Optional
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libsd.so")
+# SD_LIBRARY: another build of the library (e.g. the host-sanitized one of
+# build.build_host_sanitized); the in-tree libsd.so otherwise
+LIB_PATH = os.environ.get("SD_LIBRARY") or os.path.join(HERE, "libsd.so")
 
 # enums of sd.h
 SD_OK, SD_EINVAL, SD_EALIGN, SD_ENOMEM, SD_EDEVICE, SD_EUNSUPPORTED = range(6)

@@ -71,5 +71,48 @@ def build(verbose: bool = False) -> str:
     return LIB
 
 
+SANITIZE = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+            "-Xarch_host", "-fno-sanitize-recover=all", "-Xarch_host", "-fno-omit-frame-pointer"]
+
+
+def build_host_sanitized(out: str) -> str:
+    """The library with its host code (argument checks, planning, workspace and
+    graph management) built with AddressSanitizer and UndefinedBehaviorSanitizer,
+    into `out`: a CPU-only check that the C ABI's host
+    paths are free of memory errors and undefined behaviour.  Device code is
+    compiled as usual and not sanitised (the sanitizer flags apply to the host
+    compilation only).  Load it with the compiler's ASan runtime preloaded."""
+    bdir = out + ".objs"
+    os.makedirs(bdir, exist_ok=True)
+    srcs = sorted(glob.glob(os.path.join(CSRC, "*.hip")) + glob.glob(os.path.join(CSRC, "*.cpp")))
+
+    def one(src):
+        obj = os.path.join(bdir, os.path.basename(src) + ".o")
+        cmd = ([hipcc(), "-O1", "-Xarch_host", "-g", "-std=c++17", "-fPIC", "--offload-arch=" + ARCH,
+                "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+                "-I" + os.path.join(ROOT, "include"), "-I" + CSRC] + SANITIZE + ["-c", src, "-o", obj])
+        r = subprocess.run(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)
+        if r.returncode != 0:
+            raise RuntimeError("compile failed: %s\n%s" % (" ".join(cmd), r.stdout))
+        return obj
+
+    workers = max(1, min(len(srcs), int(os.environ.get("MAX_JOBS", os.cpu_count() or 4))))
+    with cf.ThreadPoolExecutor(max_workers=workers) as ex:
+        objs = list(ex.map(one, srcs))
+    cmd = [hipcc(), "-shared", "-fPIC", "--offload-arch=" + ARCH, "-o", out] + objs + SANITIZE
+    r = subprocess.run(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)
+    if r.returncode != 0:
+        raise RuntimeError("link failed: %s\n%s" % (" ".join(cmd), r.stdout))
+    return out
+
+
+def asan_runtime() -> str:
+    """Path of the clang ASan runtime that a sanitized build needs preloaded."""
+    root = os.environ.get("ROCM_PATH", "/opt/rocm")
+    found = sorted(glob.glob(os.path.join(root, "llvm", "lib", "clang", "*", "lib", "linux",
+                                          "libclang_rt.asan-x86_64.so")))
+    return found[-1] if found else ""
+
+
 if __name__ == "__main__":
     build(verbose=True)
