@@ -7,8 +7,10 @@
 // over a longest-first order prepared on the host), loads the cluster into LDS
 // (FP64 master positions, forces, FP32 staged positions) and runs all time
 // steps without leaving the kernel: clusters never interact, so no grid-wide
-// synchronisation is needed.  Clusters of nc <= WG particles get P = WG / nc
-// lanes per particle, each summing every P-th j; the P partial velocities are
+// synchronisation is needed.  Clusters of nc <= WG particles have the j range
+// of each particle cut into Q pieces, and the nc Q (piece, particle) items
+// dealt round-robin to the lanes (Q chosen per cluster so that the longest
+// lane's share is smallest); the Q partial velocities of a particle are
 // combined in LDS in a fixed order.  Larger clusters (up to
 // SD_BATCH_MAX_CLUSTER) give each lane ceil(nc / WG) particles.
 #include "pair_terms.h"
@@ -33,8 +35,12 @@ namespace sd {
 //   fs  f32x4[M] or f64x4[M]   forces
 //   pf  2 x f32x4[M]  FP32 staged positions (FP32 precisions), double-buffered
 //   vp  f64[3M]   previous velocities (AB2)
-//   red f64[3*max(WG, M)] per-lane partial velocities (P > 1) or the
-//                 velocities of the cluster (more particles than lanes)
+//   red f64[3*max(B_ITEMS_PER_LANE WG, M)] partial velocities of the
+//                 (piece, particle) items, or the velocities of the cluster
+//                 (more particles than lanes)
+// partial sums per lane of the work-group (see b_pieces)
+constexpr int B_ITEMS_PER_LANE = 2;
+
 struct LdsLayout {
     size_t xs1, fs, pf, pf1, vp, red, total;
 };
@@ -58,7 +64,8 @@ __host__ __device__ inline LdsLayout lds_layout(int max_size, int precision, int
     L.vp = o;
     if (integrator == SD_AB2) o += lds_round(M * 3 * sizeof(double));
     L.red = o;
-    o += lds_round((size_t)(wg > max_size ? wg : max_size) * 3 * sizeof(double));
+    const size_t items = (size_t)B_ITEMS_PER_LANE * wg;
+    o += lds_round((items > M ? items : M) * 3 * sizeof(double));
     L.total = o;
     return L;
 }
@@ -70,10 +77,10 @@ size_t batched_lds_bytes(int max_size, int precision, int integrator, int wg)
 
 
 // Velocity (pair part, physical units, self term excluded) of particle i from
-// the j = sub, sub + P, ... of the cluster held in LDS.
-// PREC: SD_FP32_KAHAN (Kahan once per group of 4 terms), SD_FP32_PLAIN, SD_FP64.
+// the particles j0 <= j < j1 of the cluster held in LDS.
+// PREC: SD_FP32_KAHAN (Kahan once per block of 16 terms), SD_FP32_PLAIN, SD_FP64.
 template <int TENSOR, int PREC>
-__device__ __forceinline__ void b_velocity(int i, int sub, int P, int nc, const double* xs,
+__device__ __forceinline__ void b_velocity(int i, int j0, int j1, const double* xs,
                                            const void* fsv, const float4* pf, const PairConst& pc,
                                            double* v)
 {
@@ -82,7 +89,7 @@ __device__ __forceinline__ void b_velocity(int i, int sub, int P, int nc, const 
         const double4* fs = (const double4*)fsv;
         const double xi0 = xs[3 * i], xi1 = xs[3 * i + 1], xi2 = xs[3 * i + 2];
         double a0 = 0.0, a1 = 0.0, a2 = 0.0;
-        for (int j = sub; j < nc; j += P) {
+        for (int j = j0; j < j1; ++j) {
             const double dx = xi0 - xs[3 * j], dy = xi1 - xs[3 * j + 1], dz = xi2 - xs[3 * j + 2];
             const double4 fj = fs[j];
             const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
@@ -110,37 +117,42 @@ __device__ __forceinline__ void b_velocity(int i, int sub, int P, int nc, const 
     constexpr bool KAHAN = PREC == SD_FP32_KAHAN;
     const float4* fs = (const float4*)fsv;
     const float4 pi = pf[i];
-    const float gamma = pc.gamma_f, m3g = pc.m3gamma_f, thr2 = pc.thr2_f;
+    // the constants in VGPRs: a VALU instruction with an SGPR operand issues
+    // at half rate on gfx950
+    float gamma = pc.gamma_f, m3g = pc.m3gamma_f, thr2 = pc.thr2_f;
+    asm volatile("" : "+v"(gamma), "+v"(m3g), "+v"(thr2));
     float s0 = 0.f, s1 = 0.f, s2 = 0.f, c0 = 0.f, c1 = 0.f, c2 = 0.f;
-    // groups of 4 j (j, j + P, j + 2P, j + 3P): one near test per group; pairs
-    // below the threshold are evaluated in FP64 from the FP64 positions and get
-    // r^2 = +inf (an exact zero) in the FP32 code; Kahan once per group
-    int j = sub;
-    for (; j + 3 * P < nc; j += 4 * P) {
+    // four consecutive j into the running block sum y: one near test per four
+    // (pairs below the threshold are evaluated in FP64 from the FP64 positions
+    // and get r^2 = +inf, an exact zero, in the FP32 code)
+    auto group4 = [&](int j, float& y0, float& y1, float& y2) {
+        // one group's data live at a time (overlapping four groups of a block
+        // doubles the register count and halves the resident waves)
+        __builtin_amdgcn_sched_barrier(0);
         float4 pj[4], fj[4];
         float dx[4], dy[4], dz[4], r2[4];
-        float rmin = 3.0e38f;
+        float rmin = 0.0f;
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
-            pj[u] = pf[j + u * P];
-            fj[u] = fs[j + u * P];
+            pj[u] = pf[j + u];
+            fj[u] = fs[j + u];
             dx[u] = pi.x - pj[u].x;
             dy[u] = pi.y - pj[u].y;
             dz[u] = pi.z - pj[u].z;
             r2[u] = fmaf(dx[u], dx[u], fmaf(dy[u], dy[u], dz[u] * dz[u]));
-            rmin = fminf(rmin, r2[u]);
+            rmin = u == 0 ? r2[0] : fminf(rmin, r2[u]);
         }
         if (__builtin_amdgcn_ballot_w64(rmin < thr2) != 0) {
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
-                const int jj = j + u * P;
+                const int jj = j + u;
                 if (r2[u] < thr2 && jj != i)
                     near_term<TENSOR>(pc, xs[3 * i] - xs[3 * jj], xs[3 * i + 1] - xs[3 * jj + 1],
-                                   xs[3 * i + 2] - xs[3 * jj + 2], fj[u].x, fj[u].y, fj[u].z, nv[0], nv[1], nv[2]);
+                                      xs[3 * i + 2] - xs[3 * jj + 2], fj[u].x, fj[u].y, fj[u].z,
+                                      nv[0], nv[1], nv[2]);
                 r2[u] = (r2[u] < thr2) ? __builtin_inff() : r2[u];
             }
         }
-        float y0 = KAHAN ? -c0 : s0, y1 = KAHAN ? -c1 : s1, y2 = KAHAN ? -c2 : s2;
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
             const float rinv = __builtin_amdgcn_rsqf(r2[u]);
@@ -155,6 +167,9 @@ __device__ __forceinline__ void b_velocity(int i, int sub, int P, int nc, const 
             y1 = fmaf(A, fj[u].y, fmaf(sB, dy[u], y1));
             y2 = fmaf(A, fj[u].z, fmaf(sB, dz[u], y2));
         }
+    };
+    // a block sum seeded with the negated compensation, then one compensated add
+    auto commit = [&](float y0, float y1, float y2) {
         if (KAHAN) {
             const float t0 = s0 + y0, t1 = s1 + y1, t2 = s2 + y2;
             c0 = (t0 - s0) - y0;
@@ -168,8 +183,20 @@ __device__ __forceinline__ void b_velocity(int i, int sub, int P, int nc, const 
             s1 = y1;
             s2 = y2;
         }
+    };
+    int j = j0;
+    for (; j + 16 <= j1; j += 16) {   // blocks of 16 terms
+        float y0 = KAHAN ? -c0 : s0, y1 = KAHAN ? -c1 : s1, y2 = KAHAN ? -c2 : s2;
+#pragma unroll 1
+        for (int g = 0; g < 16; g += 4) group4(j + g, y0, y1, y2);
+        commit(y0, y1, y2);
     }
-    for (; j < nc; j += P) {
+    for (; j + 4 <= j1; j += 4) {     // then blocks of 4
+        float y0 = KAHAN ? -c0 : s0, y1 = KAHAN ? -c1 : s1, y2 = KAHAN ? -c2 : s2;
+        group4(j, y0, y1, y2);
+        commit(y0, y1, y2);
+    }
+    for (; j < j1; ++j) {             // and single terms
         const float4 pj = pf[j];
         const float4 fj = fs[j];
         const float dx = pi.x - pj.x, dy = pi.y - pj.y, dz = pi.z - pj.z;
@@ -177,7 +204,8 @@ __device__ __forceinline__ void b_velocity(int i, int sub, int P, int nc, const 
         if (r2 < thr2) {
             if (j != i)
                 near_term<TENSOR>(pc, xs[3 * i] - xs[3 * j], xs[3 * i + 1] - xs[3 * j + 1],
-                               xs[3 * i + 2] - xs[3 * j + 2], fj.x, fj.y, fj.z, nv[0], nv[1], nv[2]);
+                                  xs[3 * i + 2] - xs[3 * j + 2], fj.x, fj.y, fj.z, nv[0], nv[1],
+                                  nv[2]);
             continue;
         }
         const float rinv = __builtin_amdgcn_rsqf(r2);
@@ -188,33 +216,42 @@ __device__ __forceinline__ void b_velocity(int i, int sub, int P, int nc, const 
             Bt = rinv3 * fmaf(m3g, rinv2, 1.0f);
         }
         const float sB = Bt * fmaf(dx, fj.x, fmaf(dy, fj.y, dz * fj.z));
-        if (KAHAN) {
-            const float y0 = fmaf(A, fj.x, fmaf(sB, dx, -c0));
-            const float y1 = fmaf(A, fj.y, fmaf(sB, dy, -c1));
-            const float y2 = fmaf(A, fj.z, fmaf(sB, dz, -c2));
-            const float t0 = s0 + y0, t1 = s1 + y1, t2 = s2 + y2;
-            c0 = (t0 - s0) - y0;
-            c1 = (t1 - s1) - y1;
-            c2 = (t2 - s2) - y2;
-            s0 = t0;
-            s1 = t1;
-            s2 = t2;
-        } else {
-            s0 = fmaf(A, fj.x, fmaf(sB, dx, s0));
-            s1 = fmaf(A, fj.y, fmaf(sB, dy, s1));
-            s2 = fmaf(A, fj.z, fmaf(sB, dz, s2));
-        }
+        const float y0 = fmaf(A, fj.x, fmaf(sB, dx, KAHAN ? -c0 : s0));
+        const float y1 = fmaf(A, fj.y, fmaf(sB, dy, KAHAN ? -c1 : s1));
+        const float y2 = fmaf(A, fj.z, fmaf(sB, dz, KAHAN ? -c2 : s2));
+        commit(y0, y1, y2);
     }
     v[0] = pc.alpha * ((double)s0 - (double)c0) + nv[0];
     v[1] = pc.alpha * ((double)s1 - (double)c1) + nv[1];
     v[2] = pc.alpha * ((double)s2 - (double)c2) + nv[2];
 }
 
+// Pieces per particle for a cluster of nc <= WG particles: the j range of each
+// particle is cut into Q pieces of ceil(nc / Q), and the nc Q (piece,
+// particle) items are dealt round-robin to the WG lanes.  Q minimises the
+// longest lane's share, ceil(nc Q / WG) ceil(nc / Q), with at most
+// B_ITEMS_PER_LANE WG items (the LDS of the partial sums); ties take the
+// smaller Q.
+
+__host__ __device__ inline int b_pieces(int nc, int wg)
+{
+    int best_q = 1;
+    long best = -1;
+    for (int q = 1; q <= nc && nc * q <= B_ITEMS_PER_LANE * wg; ++q) {
+        const long w = (long)((nc * q + wg - 1) / wg) * (long)((nc + q - 1) / q);
+        if (best < 0 || w < best) {
+            best = w;
+            best_q = q;
+        }
+    }
+    return best_q;
+}
+
 // RUN: `steps` steps per cluster, positions written back to x.
 // APPLY (steps < 0): one product, velocities written to vel.
 // Per step: every lane computes its share of the velocities from one copy of
 // the positions, the owners of the particles write the next positions to the
-// other copy, and one barrier ends the step (two when P > 1: the partial
+// other copy, and one barrier ends the step (two when Q > 1: the partial
 // velocities of a particle are summed by its owner after a barrier).
 template <int TENSOR, int PREC, int INTEG, int WG>
 __global__ void __launch_bounds__(WG)
@@ -257,7 +294,12 @@ k_batched(BatchDev b, PairConst pc, double* __restrict__ x, const void* __restri
                 ((float4*)fs)[k] = ((const float4*)frc)[g];
         }
         __syncthreads();
-        const int P = nc <= BB ? BB / nc : 1;
+        // nc <= BB: Q pieces per particle, items q nc + i dealt round-robin
+        // (consecutive lanes take consecutive particles of one piece, so a
+        // wave's j reads are LDS broadcasts); larger clusters: rows of BB
+        // particles per lane
+        const int Q = nc <= BB ? b_pieces(nc, BB) : 1;
+        const int C = (nc + Q - 1) / Q;
         const int rows = nc <= BB ? 1 : (nc + BB - 1) / BB;
         const int nsteps = steps < 0 ? 1 : steps;
         // current copy (read this step) and next copy (written this step)
@@ -268,29 +310,32 @@ k_batched(BatchDev b, PairConst pc, double* __restrict__ x, const void* __restri
         for (int st = 0; st < nsteps; ++st) {
             // velocities (pair part) of the particles this lane owns
             double v[3] = { 0.0, 0.0, 0.0 };  // rows == 1: the owner's velocity
-            if (P > 1) {
-                const int i = t / P, sub = t % P;
-                double w[3] = { 0.0, 0.0, 0.0 };
-                if (i < nc) b_velocity<TENSOR, PREC>(i, sub, P, nc, xs, fs, pf, pc, w);
-                red[3 * t] = w[0];
-                red[3 * t + 1] = w[1];
-                red[3 * t + 2] = w[2];
-                __syncthreads();
-                if (sub == 0 && i < nc)
-                    for (int u = 0; u < P; ++u) {
-                        v[0] += red[3 * (t + u)];
-                        v[1] += red[3 * (t + u) + 1];
-                        v[2] += red[3 * (t + u) + 2];
-                    }
+            if (rows == 1 && Q == 1) {
+                if (t < nc) b_velocity<TENSOR, PREC>(t, 0, nc, xs, fs, pf, pc, v);
             } else if (rows == 1) {
-                if (t < nc) b_velocity<TENSOR, PREC>(t, 0, 1, nc, xs, fs, pf, pc, v);
+                for (int it = t; it < nc * Q; it += BB) {
+                    const int q = it / nc, i = it - q * nc;
+                    const int j0 = q * C, j1 = min(j0 + C, nc);
+                    double w[3];
+                    b_velocity<TENSOR, PREC>(i, j0, j1, xs, fs, pf, pc, w);
+                    red[3 * it] = w[0];
+                    red[3 * it + 1] = w[1];
+                    red[3 * it + 2] = w[2];
+                }
+                __syncthreads();
+                if (t < nc)
+                    for (int q = 0; q < Q; ++q) {   // the pieces in order
+                        v[0] += red[3 * (q * nc + t)];
+                        v[1] += red[3 * (q * nc + t) + 1];
+                        v[2] += red[3 * (q * nc + t) + 2];
+                    }
             } else {
                 // rows of BB particles per lane: velocities to this lane's slots
                 for (int r = 0; r < rows; ++r) {
                     const int i = t + r * BB;
                     if (i >= nc) break;
                     double w[3];
-                    b_velocity<TENSOR, PREC>(i, 0, 1, nc, xs, fs, pf, pc, w);
+                    b_velocity<TENSOR, PREC>(i, 0, nc, xs, fs, pf, pc, w);
                     red[3 * i] = w[0];
                     red[3 * i + 1] = w[1];
                     red[3 * i + 2] = w[2];
@@ -298,9 +343,8 @@ k_batched(BatchDev b, PairConst pc, double* __restrict__ x, const void* __restri
             }
             // owners: velocity out (APPLY) or the next positions into the other copy
             for (int r = 0; r < rows; ++r) {
-                const int i = (P > 1) ? t / P : t + r * BB;
-                const bool own = (P > 1) ? (t % P == 0 && i < nc) : (i < nc);
-                if (!own) continue;
+                const int i = t + r * BB;
+                if (i >= nc) continue;
                 const double w0 = rows == 1 ? v[0] : red[3 * i];
                 const double w1 = rows == 1 ? v[1] : red[3 * i + 1];
                 const double w2 = rows == 1 ? v[2] : red[3 * i + 2];

@@ -5,9 +5,10 @@
 // the work-group ("small tiling") or by the whole work-group ("tiling").
 //
 // Maps (p = 131, M = 64, the wavefront size): linear k, strided k p mod N,
-// unordered (k p + j M) mod N with j the global thread id of the reading
-// (naive) or loading (tiled) thread.  The indices advance by adding p mod N
-// and subtracting N on overflow, so no integer division sits in the loop.
+// unordered (k p + g M) mod N with g the global thread id of the reading
+// (direct) or fetching (staged) thread.  The indices advance by adding a
+// precomputed increment mod N and subtracting N on overflow, so no integer
+// division sits in the loop.
 #include "sd.h"
 #include "sd_host.h"
 #include "sd_internal.h"
@@ -22,99 +23,102 @@ constexpr int MB_WAVE = 64;
 __device__ __forceinline__ float zero_of(float) { return 0.0f; }
 __device__ __forceinline__ float4 zero_of(float4) { return make_float4(0.0f, 0.0f, 0.0f, 0.0f); }
 
-// index of access k for thread j
+// Position in the index map of App. A: element k of the sequence read by the
+// thread with global id `owner` (the reader for the direct kernel, the loader
+// for the staged ones).  Linear: k; strided: k p mod N; unordered:
+// (k p + owner M) mod N.  advance(d) moves from k to k + d, with d p mod N
+// precomputed, by one add and one conditional subtract.
 template <int MAP>
-__device__ __forceinline__ unsigned mb_start(unsigned j, unsigned N)
-{
-    return MAP == 2 ? (unsigned)(((unsigned long long)j * MB_M) % N) : 0u;
-}
+struct MapCursor {
+    unsigned at;     // current index into the array
+    unsigned hop;    // index increment of one advance (mod N)
+    unsigned N;
+    __device__ MapCursor(unsigned k0, unsigned owner, unsigned stride, unsigned N_)
+        : N(N_)
+    {
+        const unsigned long long p = MAP == 0 ? 1ull : MB_P % N_;
+        const unsigned long long base = MAP == 2 ? (unsigned long long)owner * MB_M : 0ull;
+        at = (unsigned)(((unsigned long long)k0 * p + base) % N_);
+        hop = (unsigned)(((unsigned long long)stride * p) % N_);
+    }
+    __device__ __forceinline__ void advance()
+    {
+        at += hop;
+        if (at >= N) at -= N;
+    }
+};
 
-template <int MAP>
-__device__ __forceinline__ unsigned mb_next(unsigned idx, unsigned step, unsigned N)
-{
-    if (MAP == 0) return idx + 1;
-    idx += step;
-    return idx >= N ? idx - N : idx;
-}
-
+// Direct ("naive"): every thread sums its own element and then the whole
+// map sequence k = 0 .. N-1 straight from memory.  Threads past N run the
+// loop too (on in-bounds indices), so that indices common to a wave stay
+// wave-uniform and may be served by the scalar cache.
 template <typename T, int MAP>
 __global__ void __launch_bounds__(MB_BLOCK) k_mb_naive(const T* __restrict__ in, T* __restrict__ out,
-                                                       unsigned N, unsigned step)
+                                                       unsigned N)
 {
-    // every lane runs the loop (padding lanes j >= N too, reading in-bounds
-    // elements), so a wave-uniform index stays uniform and the compiler may
-    // serve it from the scalar cache
-    const unsigned j = blockIdx.x * MB_BLOCK + threadIdx.x;
-    T sum = j < N ? in[j] : zero_of(T());
-    unsigned idx = mb_start<MAP>(j, N);
+    const unsigned me = blockIdx.x * MB_BLOCK + threadIdx.x;
+    T acc = me < N ? in[me] : zero_of(T());
+    MapCursor<MAP> cur(0u, me, 1u, N);
 #pragma unroll 8
     for (unsigned k = 0; k < N; ++k) {
-        sum += in[idx];
-        idx = mb_next<MAP>(idx, step, N);
+        acc += in[cur.at];
+        cur.advance();
     }
-    if (j < N) out[j] = sum;
+    if (me < N) out[me] = acc;
 }
 
-// TILE = MB_WAVE: small tiling (the first wave loads); TILE = MB_BLOCK: tiling.
-template <typename T, int MAP, int TILE>
+// Staged ("small tiling" with LOADERS = one wave, "tiling" with LOADERS = the
+// work-group): the sequence is read in tiles of LOADERS elements, loader t
+// fetching element c LOADERS + t of tile c through ITS OWN map (unordered:
+// offset by the loader's global id), and every thread of the work-group sums
+// the tile from LDS in order.  Two LDS buffers: tile c + 1 is fetched while
+// tile c is summed, one barrier per tile.
+template <typename T, int MAP, int LOADERS>
 __global__ void __launch_bounds__(MB_BLOCK) k_mb_tiled(const T* __restrict__ in, T* __restrict__ out,
-                                                       unsigned N, unsigned step)
+                                                       unsigned N)
 {
-    __shared__ T s_data[TILE];
-    const unsigned n = threadIdx.x;
-    const unsigned j = blockIdx.x * MB_BLOCK + n;
-    T sum = j < N ? in[j] : zero_of(T());
-    // a loading thread n < TILE reads elements m + n, m = 0, TILE, 2 TILE, ...
-    // advance from m to m + TILE: idx += TILE p mod N
-    const unsigned tstep = (MAP == 0) ? TILE : (unsigned)(((unsigned long long)TILE * step) % N);
-    unsigned idx = 0;
-    if (n < TILE) {
-        // index of element n for this loader
-        if (MAP == 0) idx = n;
-        else {
-            idx = (unsigned)(((unsigned long long)n * step) % N);
-            if (MAP == 2) {
-                idx += mb_start<MAP>(j, N);
-                if (idx >= N) idx -= N;
-            }
+    __shared__ T stage[2][LOADERS];
+    const unsigned lt = threadIdx.x;
+    const unsigned me = blockIdx.x * MB_BLOCK + lt;
+    const bool loader = lt < (unsigned)LOADERS;
+    T acc = me < N ? in[me] : zero_of(T());
+    MapCursor<MAP> cur(loader ? lt : 0u, me, LOADERS, N);
+    const unsigned tiles = (N + LOADERS - 1) / LOADERS;
+    auto fetch = [&](unsigned c, int b) {
+        if (loader) {
+            stage[b][lt] = c * LOADERS + lt < N ? in[cur.at] : zero_of(T());
+            cur.advance();
         }
-    }
-    for (unsigned m = 0; m < N; m += TILE) {
-        if (n < TILE) s_data[n] = (m + n < N) ? in[idx] : zero_of(T());
-        __syncthreads();
-        const unsigned kend = (N - m < (unsigned)TILE) ? N - m : (unsigned)TILE;
-        if (kend == (unsigned)TILE) {
+    };
+    fetch(0u, 0);
+    __syncthreads();
+    for (unsigned c = 0; c < tiles; ++c) {
+        const int b = (int)(c & 1u);
+        if (c + 1 < tiles) fetch(c + 1, b ^ 1);
+        const unsigned cnt = N - c * LOADERS < (unsigned)LOADERS ? N - c * LOADERS : LOADERS;
+        if (cnt == (unsigned)LOADERS) {
 #pragma unroll 16
-            for (unsigned k = 0; k < (unsigned)TILE; ++k) sum += s_data[k];
+            for (unsigned e = 0; e < (unsigned)LOADERS; ++e) acc += stage[b][e];
         } else {
-            for (unsigned k = 0; k < kend; ++k) sum += s_data[k];
+            for (unsigned e = 0; e < cnt; ++e) acc += stage[b][e];
         }
         __syncthreads();
-        if (n < TILE) {
-            if (MAP == 0) idx += TILE;
-            else {
-                idx += tstep;
-                if (idx >= N) idx -= N;
-            }
-        }
     }
-    if (j < N) out[j] = sum;
+    if (me < N) out[me] = acc;
 }
 
 template <typename T, int MAP>
 static hipError_t mb_launch_t(int kind, const void* in, void* out, unsigned N, hipStream_t st)
 {
     const dim3 grid((N + MB_BLOCK - 1) / MB_BLOCK), block(MB_BLOCK);
-    const unsigned step = MB_P % N;
     if (kind == SD_MB_NAIVE)
-        hipLaunchKernelGGL((k_mb_naive<T, MAP>), grid, block, 0, st, (const T*)in, (T*)out, N,
-                           step);
+        hipLaunchKernelGGL((k_mb_naive<T, MAP>), grid, block, 0, st, (const T*)in, (T*)out, N);
     else if (kind == SD_MB_SMALLTILING)
         hipLaunchKernelGGL((k_mb_tiled<T, MAP, MB_WAVE>), grid, block, 0, st, (const T*)in,
-                           (T*)out, N, step);
+                           (T*)out, N);
     else
         hipLaunchKernelGGL((k_mb_tiled<T, MAP, MB_BLOCK>), grid, block, 0, st, (const T*)in,
-                           (T*)out, N, step);
+                           (T*)out, N);
     return hipGetLastError();
 }
 
