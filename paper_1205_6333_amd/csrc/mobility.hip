@@ -1425,7 +1425,8 @@ __global__ void __launch_bounds__(SYM_RUN)
 k_sym_fold_near(const float* __restrict__ jpart, const float4* __restrict__ pos,
                 const float4* __restrict__ frc, const double* __restrict__ x64, int n, int B,
                 int wpb, SymShape sh, PairConst pc, const uint8_t* __restrict__ flags,
-                double* __restrict__ out)
+                double* __restrict__ out, const double* __restrict__ partial, double mu0,
+                double* __restrict__ vel)
 {
     constexpr int FOLD_CAP = 256;   // candidates listed before their records are loaded
     __shared__ float4 s_pos[FOLD_CAP];
@@ -1628,9 +1629,19 @@ k_sym_fold_near(const float* __restrict__ jpart, const float4* __restrict__ pos,
     if (cnt > 0) flush();
     count_premise_lanes(psub, pco);
     if (q < n) {
-        out[q] = v0;
-        out[(size_t)n + q] = v1;
-        out[2 * (size_t)n + q] = v2;
+        if (vel) {
+            // the merge: mu0 F + rows 0 .. isplits in order + this row (k_merge's sum)
+            const float4 fq = frc[q];
+            double w0 = mu0 * (double)fq.x, w1 = mu0 * (double)fq.y, w2 = mu0 * (double)fq.z;
+            add_split_rows(partial, sh.isplits + 1, n, q, w0, w1, w2);
+            vel[3 * (size_t)q + 0] = w0 + v0;
+            vel[3 * (size_t)q + 1] = w1 + v1;
+            vel[3 * (size_t)q + 2] = w2 + v2;
+        } else {
+            out[q] = v0;
+            out[(size_t)n + q] = v1;
+            out[2 * (size_t)n + q] = v2;
+        }
     }
 }
 
@@ -1793,7 +1804,7 @@ static hipError_t launch_f32_sym(const PairLaunch& L, const float4* pos, const f
 
 hipError_t launch_pair_fold(const PairLaunch& L, int tensor, const float4* pos, const float4* frc,
                             const double* x64, int n, const PairConst& pc, double* partial,
-                            hipStream_t st)
+                            hipStream_t st, double mu0, double* vel)
 {
     if (L.variant != 2) return hipSuccess;
     const SymShape sh = sym_shape_of(L, n);
@@ -1804,7 +1815,8 @@ hipError_t launch_pair_fold(const PairLaunch& L, int tensor, const float4* pos, 
     const bool per = pc.box > 0.0;
 #define SD_FOLD(T, P)                                                                      \
     hipLaunchKernelGGL((k_sym_fold_near<T, P>), dim3(sh.nb * (B / SYM_RUN)), dim3(SYM_RUN), 0, \
-                       st, jpart, pos, frc, x64, n, B, L.block / 64, sh, pc, flags, out)
+                       st, jpart, pos, frc, x64, n, B, L.block / 64, sh, pc, flags, out,   \
+                       partial, mu0, vel)
     if (tensor == T_OSEEN) {
         if (per) SD_FOLD(T_OSEEN, true); else SD_FOLD(T_OSEEN, false);
     } else {

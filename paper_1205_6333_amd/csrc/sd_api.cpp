@@ -370,8 +370,9 @@ PairConst pair_const(const sd_params* p)
 // through *splits_out.  partial is sized by the caller via partial_bytes().
 sd_status run_pair(const sd_params* p, int64_t n, const void* pos, const void* frc,
                    const double* x64, int32_t prec, double* partial, const PairLaunch& L,
-                   hipStream_t st)
+                   hipStream_t st, double* vel, bool* merged)
 {
+    if (merged) *merged = false;
     const PairConst pc = pair_const(p);
     hipEvent_t ev;
     prof_begin(st, &ev);
@@ -383,9 +384,12 @@ sd_status run_pair(const sd_params* p, int64_t n, const void* pos, const void* f
         e = launch_pair_f32(L, p->tensor, L.acc, (const float4*)pos, (const float4*)frc, x64,
                             (int)n, pc, partial, st);
     prof_end(st, ev);
+    const bool fuse = vel && prec != SD_FP64 && L.variant == 2;
     if (e == hipSuccess && prec != SD_FP64)
         e = launch_pair_fold(L, p->tensor, (const float4*)pos, (const float4*)frc, x64, (int)n, pc,
-                             partial, st);
+                             partial, st, 1.0 / (6.0 * M_PI * p->eta * p->a),
+                             fuse ? vel : nullptr);
+    if (e == hipSuccess && fuse && merged) *merged = true;
     if (e != hipSuccess) return fail(SD_EDEVICE, "pair kernel launch: %s", hipGetErrorString(e));
     return SD_OK;
 }
@@ -502,7 +506,11 @@ sd_status mobility_apply(const sd_params* p, int64_t n, const void* pos, const v
         if (e != hipSuccess) return fail(SD_EDEVICE, "stage launch: %s", hipGetErrorString(e));
         pos_k = q;
     }
-    if ((st = run_pair(p, n, pos_k, force, nullptr, precision, (double*)partial, L, hs))) return st;
+    bool merged = false;
+    if ((st = run_pair(p, n, pos_k, force, nullptr, precision, (double*)partial, L, hs, vel,
+                       &merged)))
+        return st;
+    if (merged) return SD_OK;   // the pair-symmetric kernel's fold wrote vel
     hipError_t e = (precision == SD_FP64)
                        ? launch_merge_f64((double*)partial, L.splits, (int)n, (const double4*)force,
                                           1.0 / (6.0 * M_PI * p->eta * p->a), vel, hs)

@@ -55,9 +55,11 @@ sd_status check_config(int32_t prec, const sd_kernel_config& c);
 PairConst pair_const(const sd_params* p);
 PairLaunch plan_pair(int32_t prec, int64_t n);
 size_t partial_bytes(const PairLaunch& L, int64_t n);
+// vel (may be null): for the pair-symmetric kernel the product is finished
+// here (the fold merges into vel; *merged is set), else the caller merges.
 sd_status run_pair(const sd_params* p, int64_t n, const void* pos, const void* frc,
                    const double* x64, int32_t prec, double* partial, const PairLaunch& L,
-                   hipStream_t st);
+                   hipStream_t st, double* vel = nullptr, bool* merged = nullptr);
 
 void batch_release_graphs();
 void run_graphs_release();

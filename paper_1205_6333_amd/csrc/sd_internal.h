@@ -129,9 +129,12 @@ hipError_t launch_pair_f64(const PairLaunch& L, int tensor, const double4* pos, 
 // partials and the near-pair flags the pair kernel left in the workspace.
 // pos/frc: the records the pair kernel read; x64 as for launch_pair_f32.
 // Enqueue after the pair kernel, before anything reads the partial rows.
+// With vel (f64[3n]) given, the fold also does the merge: vel = mu0 F + the
+// split rows in order + the folded row, the sum k_merge forms, bit for bit,
+// and the folded row is not written.
 hipError_t launch_pair_fold(const PairLaunch& L, int tensor, const float4* pos, const float4* frc,
                             const double* x64, int n, const PairConst& pc, double* partial,
-                            hipStream_t st);
+                            hipStream_t st, double mu0 = 0.0, double* vel = nullptr);
 
 // v_i = mu0 F_i + sum_s partial_s (fixed order).
 // Read the current device's counts of pairs with 0 < r < 2a and r = 0 met by

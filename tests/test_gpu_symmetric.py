@@ -235,3 +235,29 @@ def test_sym_error_does_not_grow_with_block_count(sd, orc):
         _check(vr, ref, 0, name)
     assert errs["sym"][0] <= 1.5 * errs["plain"][0] + 1e-8
     assert errs["sym"][1] <= 1.5 * errs["plain"][1] + 1e-7
+
+
+def test_sym_near_records_hold_no_state(sd, orc):
+    """The near records of the pair-symmetric kernel are rewritten by every
+    product: an overlapping suspension gives bitwise the same velocities
+    before and after a product of a suspension with no near pair (and of one
+    of another size), and each matches the oracle."""
+    import torch
+    rng = np.random.default_rng(495)
+    n = 3000
+    xa = rng.uniform(0.0, 28.0, size=(n, 3))          # many overlaps
+    xb = W.random_suspension(n, phi=0.05, seed=496)     # none
+    xc = rng.uniform(0.0, 20.0, size=(1700, 3))
+    f = W.gaussian_forces(n, seed=497)
+    p = sd.params(overlap=True)
+    for cfg in (_cfg(256, 5, 32, 2), _cfg(256, 3, 8, 2), _cfg(128, 2, 0, 1)):
+        prec = 2 if cfg["kahan_block"] == 0 else 0
+        first = _apply(sd, xa, f, prec, p, cfg)
+        _check(first, orc.mobility(orc.params(overlap=True), W.round_to_f32(xa),
+                                   W.round_to_f32(f)), prec, "overlapping", cfg)
+        vb = _apply(sd, xb, f, prec, p, cfg)
+        _check(vb, orc.mobility(orc.params(overlap=True), W.round_to_f32(xb),
+                                W.round_to_f32(f)), prec, "apart", cfg)
+        _apply(sd, xc, f[:1700], prec, p, cfg)
+        again = _apply(sd, xa, f, prec, p, cfg)
+        assert np.array_equal(first, again), cfg
