@@ -549,7 +549,8 @@ k_pair_f32_smem(const float4* __restrict__ pos, const float4* __restrict__ frc,
 // reduction is needed.  After a chunk each row stores its 16 j-side sums in
 // LDS; at the end of a tile the rows are added in FP64 in a fixed order and
 // written as FP32 j-side partials jpart[c][I][p] (scaled units), which
-// k_sym_fold_near adds in FP64, in a fixed order, into one more split row.
+// k_sym_fold_near adds in FP64, in a fixed order, into one more split row
+// (or, for a product, straight into the merged velocities).
 // Tiles are double-buffered: the next tile is read from HBM while the
 // current one is consumed, so a tile costs two barriers.
 //

@@ -89,10 +89,10 @@ PairLaunch shape_pair_launch(int n, int variant, int block, int splits, int ilp,
 // symmetric splits, one row of the one-sided diagonal blocks, one row of the
 // folded j side and the near pairs, so PairLaunch.splits = isplits + 2.
 // After the rows (256-byte aligned) the workspace holds the FP32 j-side
-// partials, 3 * nb * lmax floats, then (256-byte aligned) the nb x nb
-// near-pair flags (uint32, cleared by the fold kernel after use; a stale
-// nonzero flag costs one extra FP64 pass over that block pair, never a wrong
-// result).
+// partials, 3 * nb * lmax floats, then (256-byte aligned) the near-pair
+// records: one 16-byte entry per wave row and tile of the virtual range, then
+// one per wave row for its own block (see sym_flag_row in mobility.hip);
+// every product rewrites every entry it reads.
 constexpr int SYM_TJ = 128;          // j tile of the symmetric kernel
 constexpr int SYM_MAX_SPLITS = 96;
 // The particles of one wave and lane slot: SYM_RUN consecutive particles.
