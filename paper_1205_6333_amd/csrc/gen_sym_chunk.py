@@ -59,7 +59,6 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 OUT = os.path.join(HERE, "sym_chunk_asm.h")
 
 COMP = ("x", "y", "z")
-PREFETCH = os.environ.get("SD_GEN_PREFETCH", "0") == "1"
 OUT = os.environ.get("SD_GEN_OUT", OUT)
 JROW_BYTES = 16 * 128 * 4     # one component of the j-side rows: 16 rows of 128 floats
 
@@ -169,11 +168,11 @@ def gen(tensor, per):
 
     def group(g):
         k0 = 2 * g
-        # LDS: the group's positions (odd registers) were requested by the
-        # previous group (group 0: here); its forces (even) are requested now
-        # and waited for after phase 1 and the near test
-        if g == 0 or not PREFETCH:
-            load_p(g)
+        # LDS: the group's positions (odd registers) and forces (even), the
+        # forces waited for after phase 1 and the near test (loading the next
+        # group's positions a group early was measured slower: 1.54 against
+        # 1.45 ms per launch)
+        load_p(g)
         for u in range(2):
             for c in range(3):
                 E.op("ds_read_b32 %s, %s offset:%d" % (v(R.F[u][c]), v(R.addr),
@@ -201,16 +200,13 @@ def gen(tensor, per):
             mu = R.m1 if u == 0 else R.m2
             E.op("v_min_f32 %s, %s, %s" % (v(mu), v(R.R2[u][0]), v(R.R2[u][1])),
                  (R.R2[u][0], R.R2[u][1]))
-        # the next group's positions, into the registers phase 1 just freed
-        if g < 7 and PREFETCH:
-            load_p(g + 1)
         # near test of the group's four pairs (each min reads one odd and one
         # even register)
         E.op("v_min_f32 %s, %s, %s" % (v(R.m1), v(R.m1), v(R.m2)), (R.m1, R.m2))
         E.op("v_cmp_lt_f32 vcc, %s, %s" % (v(R.m1), v(R.thr2)), (R.m1, R.thr2))
         # the projections of step 0 (they need neither r^2 nor the test) sit
         # between the compare and the branch that reads its result
-        E.op("s_waitcnt lgkmcnt(%d)" % (6 if (g < 7 and PREFETCH) else 0))
+        E.op("s_waitcnt lgkmcnt(0)")
         dots(g, 0)
         E.op("s_cbranch_vccz SD_SKIP%d_%%=" % g)
         # the lanes with a near pair in this group (VCC of the test)
