@@ -447,12 +447,18 @@ sd_status sd_get_kernel_config(int32_t precision, int64_t n, sd_kernel_config* o
 
 /*
  * sd_autotune -- time candidate configurations on n synthetic particles and
- * install the fastest for that precision and size class.  report (host
- * buffer, may be NULL) receives a JSON summary, truncated to report_len.
+ * install the fastest for that precision and size class (the automatic
+ * choice is among the candidates).  report (host buffer, may be NULL)
+ * receives a JSON summary, truncated to report_len: the candidate count, the
+ * automatic choice's time ("default_ms") and the fastest shapes in order.
  * Synchronises the stream; allocates temporary device memory.
  */
 sd_status sd_autotune(const sd_params* p, int64_t n, int32_t precision, void* stream,
                       char* report, int64_t report_len);
+/* sd_autotune_clear -- drop every entry sd_autotune installed for a
+ * precision, so that the automatic choice (or a forced configuration) applies
+ * again at every size.  Host-only; no device work. */
+sd_status sd_autotune_clear(int32_t precision);
 
 /* ---------------------------------------------------------------- profiling */
 

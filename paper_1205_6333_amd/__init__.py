@@ -10,7 +10,8 @@ from .binding import (SD_AB2, SD_EULER, SD_FP32_KAHAN, SD_FP32_PLAIN, SD_FP64, S
                       SD_OVERLAP_NONE, SD_OVERLAP_RPY, SD_RPY, Batch, SdError, lib,
                       mobility_adjoint, mobility_apply, mobility_apply_batched,
                       mobility_apply_noalloc, params,
-                      sd_autotune, sd_get_kernel_config, sd_profile_enable, sd_profile_read,
+                      sd_autotune, sd_autotune_clear, sd_get_kernel_config, sd_profile_enable,
+                      sd_profile_read,
                       sd_profile_reset, sd_profile_times, sd_release, sd_run, sd_run_adjoint,
                       sd_run_batched,
                       sd_set_kernel_config, sd_step, sd_version)

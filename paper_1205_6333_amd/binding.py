@@ -102,6 +102,7 @@ def lib() -> ctypes.CDLL:
             "sd_set_kernel_config": [i32, ctypes.POINTER(SdKernelConfig)],
             "sd_get_kernel_config": [i32, i64, ctypes.POINTER(SdKernelConfig)],
             "sd_autotune": [P, i64, i32, vp, ctypes.c_char_p, i64],
+            "sd_autotune_clear": [i32],
             "sd_pack": [i64, dp, vp, i32, vp],
             "lubrication_forces": [P, ctypes.POINTER(SdLub), i64, dp, dp, dp, dp, vp],
             "sd_run_lub": [P, ctypes.POINTER(SdLub), i64, dp, dp, dp, d, i64, i64, i32, i32, vp],
@@ -531,6 +532,10 @@ def sd_autotune(n: int, *, params: SdParams = None, precision: int = SD_FP32_KAH
     check(lib().sd_autotune(ctypes.byref(p), int(n), int(precision), _stream(stream), buf,
                             len(buf)))
     return buf.value.decode()
+
+
+def sd_autotune_clear(precision: int = SD_FP32_KAHAN) -> None:
+    check(lib().sd_autotune_clear(int(precision)))
 
 
 def sd_profile_enable(on: bool = True) -> None:

@@ -3,11 +3,12 @@
 //
 // Inputs: a simple cubic lattice at volume fraction 0.05 (spacing 4.37a, so
 // the timed loop is the far-field fast path, as in a dilute suspension) with a
-// fixed pattern of unit forces.  Candidates: j-data path (LDS tiles / scalar
-// cache), work-group size, particles per lane, Kahan block (FP32_KAHAN) and
-// the number of j-range splits around the automatic choice.  Each candidate
-// is warmed up once and timed over three launches with HIP events on the
-// caller's stream.
+// fixed pattern of unit forces.  Candidates: kernel variant (LDS tiles /
+// scalar cache / pair symmetry), work-group size, particles per lane, Kahan
+// block (FP32_KAHAN) and the number of j-range splits, plus the automatic
+// choice itself, so the installed entry is never one that timed slower than
+// it.  Each candidate is warmed up once and timed over three launches with
+// HIP events on the caller's stream.
 #include "sd.h"
 #include "sd_host.h"
 
@@ -28,6 +29,12 @@ struct Cand {
     sd_kernel_config c;
     float ms;
 };
+
+bool same_config(const sd_kernel_config& a, const sd_kernel_config& b)
+{
+    return a.variant == b.variant && a.block == b.block && a.splits == b.splits &&
+           a.ilp == b.ilp && a.kahan_block == b.kahan_block;
+}
 
 std::vector<sd_kernel_config> candidates(int32_t prec, int64_t n)
 {
@@ -62,8 +69,11 @@ std::vector<sd_kernel_config> candidates(int32_t prec, int64_t n)
                         out.push_back(c);
                     }
             }
-    // variant 2 (pair symmetry): FP32 only, ilp 1, kahan_block 0/4/8, blocks
-    // of 128 or 256, when its j-side workspace stays within the cap
+    // variant 2 (pair symmetry), FP32 only, when its j-side workspace fits:
+    // 128-512 lanes with one or two particles per lane, Kahan blocks of 4 or
+    // 8 (the compiled chunk loop) and, with 256 lanes and two particles per
+    // lane, 16 or 32 (the chunk loop in assembly); requested split counts of
+    // 8 to 64
     if (prec != SD_FP64)
         for (int block : { 128, 256, 512 })
             for (int ilp : { 1, 2 }) {
@@ -72,15 +82,23 @@ std::vector<sd_kernel_config> candidates(int32_t prec, int64_t n)
                 c.variant = 2;
                 c.block = block;
                 c.ilp = ilp;
-                const std::vector<int> kbs =
-                    prec == SD_FP32_KAHAN ? std::vector<int>{ 4, 8 } : std::vector<int>{ 0 };
+                std::vector<int> kbs = { 0 };
+                if (prec == SD_FP32_KAHAN) {
+                    kbs = { 4, 8 };
+                    if (block == 256 && ilp == 2) kbs.insert(kbs.end(), { 16, 32 });
+                }
                 for (int kb : kbs)
-                    for (int s : split_opts) {
+                    for (int s : { 8, 16, 32, 64 }) {
                         c.kahan_block = kb;
-                        c.splits = std::max(1, s * 256 / (block * ilp));
+                        c.splits = s;
                         out.push_back(c);
                     }
             }
+    // the automatic choice, timed last (after the clocks have ramped up)
+    out.erase(std::remove_if(out.begin(), out.end(),
+                             [&](const sd_kernel_config& c) { return same_config(c, d); }),
+              out.end());
+    out.push_back(d);
     return out;
 }
 
@@ -157,10 +175,17 @@ extern "C" sd_status sd_autotune(const sd_params* p, int64_t n, int32_t precisio
     if (res.empty()) return fail(SD_EUNSUPPORTED, "no candidate configuration ran");
     std::sort(res.begin(), res.end(), [](const Cand& a, const Cand& b) { return a.ms < b.ms; });
     set_tuned_config(precision, n, res[0].c);
+    const sd_kernel_config d = default_config(precision, n);
+    double default_ms = -1.0;   // -1: the automatic choice did not run
+    for (const Cand& r : res)
+        if (same_config(r.c, d)) default_ms = r.ms;
     if (report && report_len > 0) {
+        char dl[64];
+        snprintf(dl, sizeof dl, "%.4f", default_ms);
         std::string s = "{\"n\": " + std::to_string(n) + ", \"precision\": " +
                         std::to_string(precision) + ", \"candidates\": " +
-                        std::to_string(res.size()) + ", \"ranked\": [";
+                        std::to_string(res.size()) + ", \"default_ms\": " + dl +
+                        ", \"ranked\": [";
         for (size_t k = 0; k < res.size() && k < 12; ++k) {
             char line[256];
             snprintf(line, sizeof line,

@@ -724,6 +724,15 @@ sd_status sd_set_kernel_config(int32_t precision, const sd_kernel_config* cfg)
     return SD_OK;
 }
 
+sd_status sd_autotune_clear(int32_t precision)
+{
+    sd_status st;
+    if ((st = check_precision(precision))) return st;
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_cfg[precision].tuned.clear();
+    return SD_OK;
+}
+
 sd_status sd_get_kernel_config(int32_t precision, int64_t n, sd_kernel_config* out)
 {
     sd_status st;

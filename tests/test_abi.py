@@ -108,6 +108,9 @@ def test_kernel_config_validation(L):
         b.sd_set_kernel_config(b.SD_FP32_PLAIN, dict(variant=0, block=256, splits=1, ilp=1,
                                                      kahan_block=4))
     b.sd_set_kernel_config(b.SD_FP32_KAHAN, None)
+    for prec in (b.SD_FP32_PLAIN, b.SD_FP32_KAHAN, b.SD_FP64):
+        assert L.sd_autotune_clear(prec) == b.SD_OK
+    assert L.sd_autotune_clear(7) == b.SD_EINVAL
 
 
 def test_batch_plan_errors(L):

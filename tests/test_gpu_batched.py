@@ -164,7 +164,40 @@ def test_autotune_installs_a_valid_config(sd, orc):
     xo, fo = W.round_to_f32(x), W.round_to_f32(f)
     v = sd.mobility_apply(to_dev4(xo, torch.float32), to_dev4(fo, torch.float32))
     torch.cuda.synchronize()
+    sd.sd_autotune_clear(sd.SD_FP32_KAHAN)
     _check(v.cpu().numpy(), orc.mobility(orc.params(), xo, fo), 1e-6, cfg)
+
+
+def test_autotune_times_the_automatic_choice_and_the_assembly_shapes(sd, orc):
+    """From N = 16384 on the automatic choice is the pair-symmetric kernel with
+    its chunk loop in assembly (256 lanes, two particles per lane, Kahan block
+    32): the tuner times it beside the other shapes, installs nothing slower,
+    and the installed shape keeps parity.  Clearing restores the automatic
+    choice."""
+    import json
+    import torch
+    n = 16384
+    auto = sd.sd_get_kernel_config(sd.SD_FP32_KAHAN, n)
+    assert (auto["variant"], auto["block"], auto["ilp"], auto["kahan_block"]) == (2, 256, 2, 32)
+    rep = json.loads(sd.sd_autotune(n, precision=sd.SD_FP32_KAHAN))
+    try:
+        assert rep["default_ms"] > 0
+        ranked = rep["ranked"]
+        assert ranked[0]["ms"] <= rep["default_ms"]
+        cfg = sd.sd_get_kernel_config(sd.SD_FP32_KAHAN, n)
+        assert {k: cfg[k] for k in ("variant", "block", "splits", "ilp", "kahan_block")} == \
+            {k: ranked[0][k] for k in ("variant", "block", "splits", "ilp", "kahan_block")}
+        x = W.random_suspension(n, seed=12)
+        f = W.gaussian_forces(n, seed=13)
+        xo, fo = W.round_to_f32(x), W.round_to_f32(f)
+        v = sd.mobility_apply(to_dev4(xo, torch.float32), to_dev4(fo, torch.float32))
+        torch.cuda.synchronize()
+        rows = np.random.default_rng(5).choice(n, 512, replace=False)
+        ref = orc.mobility_rows(orc.params(), xo, fo, rows)
+        _check(v.cpu().numpy()[rows], ref, 1e-6, cfg)
+    finally:
+        sd.sd_autotune_clear(sd.SD_FP32_KAHAN)
+    assert sd.sd_get_kernel_config(sd.SD_FP32_KAHAN, n) == auto
 
 
 def test_batched_full_workload_sampled_clusters(sd, orc):
