@@ -480,7 +480,9 @@ sd_status sd_profile_times(float* ms, int64_t cap, int64_t* count);
 /*
  * sd_mean_vector -- out[0..2] = (1/n) sum_i v_i for v f64[3n] (e.g. the
  * centre-of-mass velocity of the sedimenting suspensions of Secs. 3.3 and 4).
- * One work-group sums in a fixed order: the result is deterministic.
+ * Summed in a fixed order that depends on n only (contiguous ranges of
+ * particles, then their partial sums): the result is deterministic.  Uses
+ * library workspace (24 bytes per 1024 particles, at most 24 KiB).
  * out: device f64[3].
  */
 sd_status sd_mean_vector(int64_t n, const double* v, double* out, void* stream);

@@ -112,19 +112,22 @@ __global__ void __launch_bounds__(64) k_fill_i32(int32_t* __restrict__ p, int32_
     if (k < count) p[k] = value;
 }
 
-// out = (1/n) sum_i v_i with one 256-lane work-group: lane t sums i = t, t+256,
-// ... in order, then a fixed-shape tree combines the 256 partial sums.
-__global__ void __launch_bounds__(256) k_mean_vector(const double* __restrict__ v, int64_t n,
-                                                     double* __restrict__ out)
+// out = (1/n) sum_i v_i in a fixed order, in two launches: G = mean_groups(n)
+// work-groups each sum a contiguous range of ceil(n / G) particles (lane t:
+// particles t, t + 256, ... of the range in order, then a fixed-shape tree
+// over the 256 lanes) into partial[c G + g]; one work-group then sums the G
+// partials the same way.  The grouping depends on n only, so the result does
+// not depend on the device or on the scheduling of the work-groups.
+int64_t mean_groups(int64_t n)
 {
-    __shared__ double red[3][256];
-    const int t = threadIdx.x;
-    double a0 = 0.0, a1 = 0.0, a2 = 0.0;
-    for (int64_t i = t; i < n; i += 256) {
-        a0 += v[3 * i];
-        a1 += v[3 * i + 1];
-        a2 += v[3 * i + 2];
-    }
+    const int64_t g = (n + 1023) / 1024;
+    return g < 1 ? 1 : (g > 1024 ? 1024 : g);
+}
+
+// the three lane sums of a 256-lane work-group -> lane 0, fixed shape
+__device__ __forceinline__ void tree3(double (&red)[3][256], int t, double a0, double a1,
+                                      double a2)
+{
     red[0][t] = a0;
     red[1][t] = a1;
     red[2][t] = a2;
@@ -137,12 +140,50 @@ __global__ void __launch_bounds__(256) k_mean_vector(const double* __restrict__ 
         }
         __syncthreads();
     }
+}
+
+__global__ void __launch_bounds__(256) k_mean_partial(const double* __restrict__ v, int64_t n,
+                                                      int64_t chunk, int groups,
+                                                      double* __restrict__ partial)
+{
+    __shared__ double red[3][256];
+    const int t = threadIdx.x, g = blockIdx.x;
+    const int64_t i0 = (int64_t)g * chunk;
+    const int64_t i1 = i0 + chunk < n ? i0 + chunk : n;
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+    for (int64_t i = i0 + t; i < i1; i += 256) {
+        a0 += v[3 * i];
+        a1 += v[3 * i + 1];
+        a2 += v[3 * i + 2];
+    }
+    tree3(red, t, a0, a1, a2);
+    if (t < 3) partial[(int64_t)t * groups + g] = red[t][0];
+}
+
+__global__ void __launch_bounds__(256) k_mean_final(const double* __restrict__ partial,
+                                                    int groups, int64_t n,
+                                                    double* __restrict__ out)
+{
+    __shared__ double red[3][256];
+    const int t = threadIdx.x;
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+    for (int k = t; k < groups; k += 256) {
+        a0 += partial[k];
+        a1 += partial[groups + k];
+        a2 += partial[2 * groups + k];
+    }
+    tree3(red, t, a0, a1, a2);
     if (t < 3) out[t] = red[t][0] / (double)n;
 }
 
-hipError_t launch_mean_vector(const double* v, int64_t n, double* out, hipStream_t st)
+hipError_t launch_mean_vector(const double* v, int64_t n, double* out, double* partial,
+                              hipStream_t st)
 {
-    hipLaunchKernelGGL(k_mean_vector, dim3(1), dim3(256), 0, st, v, n, out);
+    const int64_t g = mean_groups(n);
+    const int64_t chunk = (n + g - 1) / g;
+    hipLaunchKernelGGL(k_mean_partial, dim3((unsigned)g), dim3(256), 0, st, v, n, chunk, (int)g,
+                       partial);
+    hipLaunchKernelGGL(k_mean_final, dim3(1), dim3(256), 0, st, partial, (int)g, n, out);
     return hipGetLastError();
 }
 

@@ -701,7 +701,9 @@ sd_status sd_mean_vector(int64_t n, const double* v, double* out, void* stream)
     sd_status st;
     if ((st = check_n(n)) || (st = check_ptr(v, 8, "v")) || (st = check_ptr(out, 8, "out")))
         return st;
-    hipError_t e = launch_mean_vector(v, n, out, (hipStream_t)stream);
+    void* part = nullptr;
+    if ((st = ws_get(WS_MEAN, 3 * (size_t)mean_groups(n) * sizeof(double), &part))) return st;
+    hipError_t e = launch_mean_vector(v, n, out, (double*)part, (hipStream_t)stream);
     if (e != hipSuccess) return fail(SD_EDEVICE, "mean launch: %s", hipGetErrorString(e));
     return SD_OK;
 }

@@ -24,6 +24,7 @@ enum {
     WS_LUB_F,         // lubrication-corrected forces of a step
     WS_QPOS,          // fixed-point positions of a product in a periodic box
     WS_CLUSTER,       // run records of the precision study
+    WS_MEAN,          // partial sums of sd_mean_vector
     WS_COUNT
 };
 

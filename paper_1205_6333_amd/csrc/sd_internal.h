@@ -194,7 +194,10 @@ hipError_t launch_batched_apply(const BatchDev& b, int tensor, int precision, co
                                 const void* pos, const void* frc, double* vel, int n_workgroups,
                                 hipStream_t st);
 hipError_t launch_fill_i32(int32_t* p, int32_t value, int count, hipStream_t st);
-hipError_t launch_mean_vector(const double* v, int64_t n, double* out, hipStream_t st);
+// out = (1/n) sum_i v_i (deterministic); partial: f64[3 mean_groups(n)] scratch
+int64_t mean_groups(int64_t n);
+hipError_t launch_mean_vector(const double* v, int64_t n, double* out, double* partial,
+                              hipStream_t st);
 size_t batched_lds_bytes(int max_size, int precision, int integrator, int wg);
 
 }  // namespace sd
