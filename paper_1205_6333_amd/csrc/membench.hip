@@ -36,7 +36,12 @@ struct MapCursor {
     __device__ MapCursor(unsigned k0, unsigned owner, unsigned stride, unsigned N_)
         : N(N_)
     {
-        const unsigned long long p = MAP == 0 ? 1ull : MB_P % N_;
+        if (MAP == 0) {   // k itself: the increment stays a compile-time constant
+            at = k0;
+            hop = stride;
+            return;
+        }
+        const unsigned long long p = MB_P % N_;
         const unsigned long long base = MAP == 2 ? (unsigned long long)owner * MB_M : 0ull;
         at = (unsigned)(((unsigned long long)k0 * p + base) % N_);
         hop = (unsigned)(((unsigned long long)stride * p) % N_);
@@ -44,7 +49,11 @@ struct MapCursor {
     __device__ __forceinline__ void advance()
     {
         at += hop;
-        if (at >= N) at -= N;
+        // the linear map does not wrap within the N elements of a sequence
+        // (a staged loader's index past N is not read), and without the
+        // compare the compiler sees consecutive indices and merges their
+        // wave-uniform loads
+        if (MAP != 0 && at >= N) at -= N;
     }
 };
 
