@@ -200,6 +200,38 @@ def test_autotune_times_the_automatic_choice_and_the_assembly_shapes(sd, orc):
     assert sd.sd_get_kernel_config(sd.SD_FP32_KAHAN, n) == auto
 
 
+@pytest.mark.parametrize("prec,tol", [("SD_FP64", 1e-12), ("SD_FP32_PLAIN", 1e-5)])
+def test_autotune_other_precisions(sd, orc, prec, tol):
+    """The tuner for the FP64 path and for plain FP32 accumulation: it times the
+    automatic choice, installs a valid shape no slower than it, the installed
+    shape keeps parity, and clearing restores the automatic choice."""
+    import json
+    import torch
+    P = getattr(sd, prec)
+    n = 16384
+    auto = sd.sd_get_kernel_config(P, n)
+    rep = json.loads(sd.sd_autotune(n, precision=P))
+    try:
+        assert rep["default_ms"] > 0 and rep["ranked"][0]["ms"] <= rep["default_ms"]
+        cfg = sd.sd_get_kernel_config(P, n)
+        x = W.random_suspension(n, seed=14)
+        f = W.gaussian_forces(n, seed=15)
+        if P == sd.SD_FP64:
+            xo, fo = x, f
+            v = sd.mobility_apply(to_dev4(xo, torch.float64), to_dev4(fo, torch.float64),
+                                  precision=P)
+        else:
+            xo, fo = W.round_to_f32(x), W.round_to_f32(f)
+            v = sd.mobility_apply(to_dev4(xo, torch.float32), to_dev4(fo, torch.float32),
+                                  precision=P)
+        torch.cuda.synchronize()
+        rows = np.random.default_rng(6).choice(n, 256, replace=False)
+        _check(v.cpu().numpy()[rows], orc.mobility_rows(orc.params(), xo, fo, rows), tol, cfg)
+    finally:
+        sd.sd_autotune_clear(P)
+    assert sd.sd_get_kernel_config(P, n) == auto
+
+
 def test_batched_full_workload_sampled_clusters(sd, orc):
     """The 4096-cluster workload (N_c ~ U{4..256}, 100 Euler steps, dt = 0.01,
     graph launch) in its launch configuration; 48 sampled clusters (plus the
